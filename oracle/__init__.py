@@ -1,0 +1,37 @@
+"""CPU FP64 oracle for the Heisenberg-picture TFIM tensor-network method.
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product path (the HIP library, its
+Python binding) imports, links or calls this package; only the tests, the
+smoke check and the CPU-baseline leg of the benchmark do.
+
+It is a plain, slow, obviously-correct restatement of the paper
+("GPU-First Heisenberg-Picture Tensor Network Dynamics for the 2D
+Transverse-Field Ising Model"), written in NumPy/SciPy double precision:
+
+* ``lattice``  -- the k x l open lattice, its bonds, the 4-colouring and the
+                  centre site (Sec. "Model", "Trotter Decomposition",
+                  Sec. "Numerical Experiments" for the centre formula).
+* ``ptm``      -- Pauli transfer matrices of the Trotter gates, built from
+                  the trace formula (Sec. "Trotter Decomposition", Eq. trotter).
+* ``dense``    -- exact 2^N operator evolution: the plain definition of C(t)
+                  (Eq. autocorr) used as oracle-of-the-oracle.
+* ``network``  -- the method itself: Pauli-basis operator network, gate update
+                  (Sec. "Gate Update", Algorithm "Gate update"), gauge BP
+                  (Eq. bp, Eq. damping), measurement BP and the log-space Bethe
+                  evaluation with sign tracking (Eqs. bethe_raw, ze, bethe).
+* ``contract`` -- exact contraction of tiny networks (no BP), for pins.
+* ``run``      -- the time loop producing C(t) trajectories.
+
+Readings of points the paper leaves open are listed in the design doc and stated
+at the function that implements them.  The oracle shares no code with the GPU
+path; the only shared module is ``paper_2606_30985_amd.inputs`` (seeded input
+generators, no method arithmetic).
+"""
+
+from .lattice import Lattice
+from .ptm import field_ptm, coupling_ptm, pauli_matrices
+from .network import Config, OperatorNetwork
+from .run import run
+
+__all__ = ["Lattice", "field_ptm", "coupling_ptm", "pauli_matrices",
+           "Config", "OperatorNetwork", "run"]
