@@ -1,0 +1,190 @@
+/*
+ * hpt.h -- C ABI of libhpt: Heisenberg-picture tensor-network dynamics of the
+ * 2D transverse-field Ising model on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: "GPU-First Heisenberg-Picture Tensor Network Dynamics for the 2D
+ * Transverse-Field Ising Model".  The operator Z_c(t) is a network of real
+ * Pauli-basis site tensors on an open Lx x Ly lattice (Sec. "Pauli Basis
+ * Tensor Network"); each Trotter layer applies field and coupling gates
+ * (Sec. "Trotter Decomposition", Eq. trotter) through the gate update of
+ * Sec. "Gate Update" / Algorithm "Gate update", then belief-propagation
+ * sweeps (Eq. bp, Eq. damping); C(t) = Tr[Z_c(t) Z_c]/2^N (Eq. autocorr) is
+ * read out by the log-space Bethe sum with sign tracking (Eqs. bethe_raw,
+ * ze, bethe).
+ *
+ * Conventions shared by every entry point:
+ *   - Hamiltonian H = -J sum_<ij> X_i X_j - h sum_i Z_i (Eq. hamiltonian);
+ *     one step is exp(+i h dt/2 sum Z) exp(+i J dt sum XX) exp(+i h dt/2 sum Z).
+ *   - Sites v = x + Lx*y.  Legs of a site in the order U (x,y-1), D (x,y+1),
+ *     L (x-1,y), R (x+1,y), absent legs omitted, then the Pauli leg
+ *     p = 0 I, 1 X, 2 Y, 3 Z (Sec. "GPU Tensor Permutation" leg order).
+ *   - Bonds: every horizontal ((x,y),(x+1,y)) in row-major order, then every
+ *     vertical ((x,y),(x,y+1)) in row-major order.  Bond b joins v1 < v2.
+ *     Colour: horizontal x even 0, x odd 1; vertical y even 2, y odd 3.
+ *     Directed message dir 0 travels v1 -> v2, dir 1 travels v2 -> v1.
+ *   - Host tensors are float64, column-major (first listed index fastest),
+ *     dims = (chi of each present leg in U,D,L,R order, 4).
+ *   - Every function returns 0 on success or a negative HPT_E* code; the
+ *     handle is left usable after HPT_EINVAL / HPT_ENOMEM / HPT_ESTATE.
+ *   - Calls on one handle are stream-ordered on the stream given at create
+ *     and are not thread-safe; separate handles are independent.
+ *   - No device memory is allocated after hpt_create (Sec. "Zero-Malloc
+ *     Simulation Loop").
+ */
+#ifndef HPT_H
+#define HPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define HPT_OK        0
+#define HPT_EINVAL   -1   /* bad argument: dims, centre, dt == 0, chi_max < 1, bond/site index */
+#define HPT_ENOMEM   -2   /* arena smaller than hpt_required_bytes, checked before any launch */
+#define HPT_EHIP     -3   /* HIP runtime error; hpt_last_hip_error() has its text */
+#define HPT_ENUMERIC -4   /* non-finite data, zero bond matrix, SVD non-convergence */
+#define HPT_ESTATE   -5   /* call order (e.g. library not initialised) */
+
+/* precision */
+#define HPT_FP64       0  /* plain form: every step in float64 */
+#define HPT_FP32_MFMA  1  /* float32 site tensors and MFMA contractions; float64
+                             Cholesky, R-core SVD, eigensolver, BP normalisation, Bethe sum */
+
+/* QR strategy (Sec. "Adaptive QR Decomposition") */
+#define HPT_QR_ADAPTIVE    0  /* CholeskyQR2 for tall blocks, Householder otherwise or on failure */
+#define HPT_QR_HOUSEHOLDER 1  /* Householder everywhere */
+
+/* BP initialisation */
+#define HPT_BP_UNIFORM 0      /* gauge messages I/sqrt(chi) at the start of every layer */
+#define HPT_BP_WARM    1      /* continue from the messages left by the gates */
+
+/* measurement flags */
+#define HPT_FLAG_BP_NOT_CONVERGED_GAUGE (1u << 0)
+#define HPT_FLAG_BP_NOT_CONVERGED_MEAS  (1u << 1)
+#define HPT_FLAG_TRAP_CANDIDATE         (1u << 2)  /* sweeps >= trap_sweeps and delta < tol */
+#define HPT_FLAG_NORM_EXPLODED          (1u << 3)  /* gauge Bethe norm >= 2 */
+#define HPT_FLAG_DEGENERATE_CUT         (1u << 4)  /* s[chi_max-1] - s[chi_max] <= 1e-10 s[0] */
+#define HPT_FLAG_PINV_CUT               (1u << 5)  /* an environment eigenvalue was dropped */
+#define HPT_FLAG_BETHE_ZERO             (1u << 6)  /* some vs_v or Z_e was exactly zero */
+#define HPT_FLAG_QR_FALLBACK            (1u << 7)  /* CholeskyQR2 failed, Householder used */
+
+typedef struct {
+  int32_t Lx, Ly;          /* lattice, >= 1 each, Lx*Ly >= 2 */
+  double  J, h, dt;        /* coupling, field, time step (dt != 0) */
+  int32_t chi_max;         /* bond-dimension cap, >= 1 */
+  int32_t cx, cy;          /* observable site; -1,-1 -> ((Lx-1)/2, (Ly-1)/2) */
+  int32_t precision;       /* HPT_FP64 | HPT_FP32_MFMA */
+  int32_t qr_mode;         /* HPT_QR_ADAPTIVE | HPT_QR_HOUSEHOLDER */
+  int32_t chol_min_ratio;  /* CholeskyQR2 needs rows >= chol_min_ratio * cols (default 2) */
+  int32_t chol_min_cols;   /* ... and cols >= chol_min_cols (default 16); the paper's
+                              rule (Sec. "Adaptive QR Decomposition") is ratio 150, cols 150 */
+  double  eps_cut;         /* truncation cutoff relative to s_0 (Eq. truncation), 1e-11 */
+  double  eps_pinv;        /* environment eigenvalue cutoff relative to the largest, 1e-12 */
+  double  bp_alpha;        /* damping (Eq. damping), 0.5 */
+  double  bp_tol;          /* max |change| stopping rule (Eq. bp_tol), 1e-10 */
+  int32_t bp_max_sweeps;   /* 1000 */
+  int32_t bp_init;         /* HPT_BP_UNIFORM | HPT_BP_WARM */
+  double  meas_alpha;      /* measurement-BP damping; < 0 -> bp_alpha */
+  double  meas_tol;        /* measurement-BP tolerance; <= 0 -> bp_tol */
+  int32_t meas_max_sweeps; /* <= 0 -> bp_max_sweeps */
+  int32_t gauge_bp;        /* 1: run gauge BP after every layer (default); 0: skip */
+  int32_t trap_sweeps;     /* trap rule threshold (Sec. "BP Fixed-Point Multiplicity"), 30 */
+  int32_t reserved[7];
+} hpt_config;
+
+typedef struct {
+  int32_t  step;               /* layers applied since reset */
+  double   t;                  /* step * dt */
+  double   C;                  /* Bethe estimate of C(t) (Eq. bethe) */
+  double   log_abs_C;          /* sum log|vs_v| - sum log|Z_e| */
+  int32_t  sign;               /* product of the signs, 0 if C == 0 */
+  double   gate_err;           /* sum over bonds of the discarded weight in the last layer */
+  double   bethe_norm;         /* gauge-BP Bethe estimate of Tr[O^2]/2^N */
+  double   max_S_over_logchi;  /* max over bonds of S_e / log(chi_max) */
+  int32_t  gauge_sweeps, meas_sweeps;
+  double   gauge_delta, meas_delta;
+  int32_t  chi_live_max;
+  uint32_t flags;              /* HPT_FLAG_* of the last layer and this measurement */
+} hpt_measurement;
+
+typedef struct hpt_sim hpt_sim;
+
+/* Fill *cfg with the defaults listed above (3x3, J = h = 1, dt = 0.05, chi_max 8, FP64). */
+int hpt_config_default(hpt_config* cfg);
+
+/* Device bytes the handle needs for cfg (analytic memory model, Sec. "Analytic
+ * Memory Model" generalised to this library's workspace).  Host only, no GPU. */
+int hpt_required_bytes(const hpt_config* cfg, uint64_t* bytes);
+
+/* Paper's state term M_psi (Eq. mem_psi) for cfg, in bytes of the storage type. */
+int hpt_state_bytes(const hpt_config* cfg, uint64_t* bytes);
+
+/* Create a simulator.  arena: caller-owned device memory of arena_bytes
+ * (>= hpt_required_bytes, 256-byte aligned) that must outlive the handle, or
+ * NULL to let the library make one hipMalloc that hpt_destroy frees.
+ * hip_stream: a hipStream_t (NULL = the null stream).  The state is reset to t = 0. */
+int hpt_create(const hpt_config* cfg, void* arena, uint64_t arena_bytes,
+               void* hip_stream, hpt_sim** out);
+
+/* t = 0 state: psi_c = e_Z, psi_v = e_I elsewhere, every bond chi = 1, messages [[1]]. */
+int hpt_reset(hpt_sim* sim);
+
+/* nsteps Trotter layers: field half-step, 4-colour gate sweep, field
+ * half-step, gauge BP (pipeline figure of Sec. "Implementation").  Returns
+ * after the last layer's bond dimensions are known on the host. */
+int hpt_step(hpt_sim* sim, int32_t nsteps);
+
+/* One field half-step exp(+i h dt/2 Z) on every site (row a1). */
+int hpt_apply_field(hpt_sim* sim);
+
+/* The two-site gate update of Algorithm "Gate update" on one bond (rows a2-a7). */
+int hpt_apply_bond(hpt_sim* sim, int32_t bond);
+
+/* Gauge BP on the norm network until delta < bp_tol or bp_max_sweeps (row a8).
+ * init: HPT_BP_UNIFORM or HPT_BP_WARM.  sweeps/delta may be NULL. */
+int hpt_gauge_bp(hpt_sim* sim, int32_t init, int32_t* sweeps, double* delta);
+
+/* Measurement BP on the pinned network and log-space Bethe sum (row a9),
+ * plus the diagnostics of the last layer.  Synchronises the stream. */
+int hpt_measure(hpt_sim* sim, hpt_measurement* out);
+
+/* Live bond dimension of one bond. */
+int hpt_get_chi(hpt_sim* sim, int32_t bond, int32_t* chi);
+
+/* Vidal values lambda of the bond's last gate (cap >= chi), *chi receives the count. */
+int hpt_get_bond_spectrum(hpt_sim* sim, int32_t bond, double* lam, int32_t cap, int32_t* chi);
+
+/* Copy a site tensor to host (n >= product of dims); dims[0..deg] receive its shape. */
+int hpt_get_site_tensor(hpt_sim* sim, int32_t site, double* host, uint64_t n, int32_t* dims);
+
+/* Replace a site tensor; dims gives the chi of each present leg in U,D,L,R
+ * order followed by 4.  Every bond's chi must agree with both end sites
+ * before the next step: setting a tensor sets the chi of its bonds. */
+int hpt_set_site_tensor(hpt_sim* sim, int32_t site, const double* host, const int32_t* dims);
+
+/* Gauge message on bond/dir as a chi x chi column-major float64 matrix. */
+int hpt_get_messages(hpt_sim* sim, int32_t bond, int32_t dir, double* host, int32_t cap);
+int hpt_set_messages(hpt_sim* sim, int32_t bond, int32_t dir, const double* host, int32_t chi);
+
+/* Measurement message (vector of length chi) of the last hpt_measure. */
+int hpt_get_meas_messages(hpt_sim* sim, int32_t bond, int32_t dir, double* host, int32_t cap);
+
+int hpt_destroy(hpt_sim* sim);
+
+const char* hpt_strerror(int code);
+const char* hpt_last_hip_error(void);
+
+/* Permute a column-major tensor on the device (Sec. "GPU Tensor Permutation").
+ * in/out: device pointers, not overlapping; ndim <= 8; dims of the input;
+ * perm[k] = input axis that becomes output axis k; elem_size 4 or 8.
+ * Bit-exact copy.  Stream-ordered on hip_stream. */
+int hpt_permute(const void* in, void* out, int32_t ndim, const int64_t* dims,
+                const int32_t* perm, int32_t elem_size, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPT_H */

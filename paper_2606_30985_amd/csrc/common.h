@@ -1,0 +1,60 @@
+// Shared definitions of the libhpt HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <algorithm>
+
+namespace hpt {
+
+typedef __attribute__((ext_vector_type(4))) double d4;
+typedef __attribute__((ext_vector_type(4))) float f4;
+
+// Error handling: every HIP call in host code goes through HPT_HIP.
+void set_hip_error(hipError_t e, const char* what);
+#define HPT_HIP(call)                                   \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) {                             \
+      ::hpt::set_hip_error(_e, #call);                  \
+      return -3;                                        \
+    }                                                   \
+  } while (0)
+#define HPT_LAUNCH_CHECK(what)                          \
+  do {                                                  \
+    hipError_t _e = hipGetLastError();                  \
+    if (_e != hipSuccess) {                             \
+      ::hpt::set_hip_error(_e, what);                   \
+      return -3;                                        \
+    }                                                   \
+  } while (0)
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// Batched, batch-reducing GEMM on MFMA (k_gemm.hip).
+//   C[z] = alpha * sum_{r < R} op(A[z, r]) op(B[z, r]) + beta * C[z]
+// column-major operands; op(A) is M x K, op(B) is K x N.  A[z, r] starts at
+// A + z*sAz + r*sAr (same for B), C[z] at C + z*sCz.  Output type OutT is T
+// or double; with splits > 1 partial tiles go through `part` (double,
+// splits * Z * M * N entries) and a deterministic second pass.
+template <typename T>
+struct GemmDesc {
+  int M, N, K, R, Z;
+  const T* A; int64_t lda, sAz, sAr; int tA;
+  const T* B; int64_t ldb, sBz, sBr; int tB;
+  void* C; int64_t ldc, sCz; int c_double;
+  double alpha, beta;
+};
+template <typename T>
+int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s);
+
+// Tensor permutation (k_permute.hip).
+int permute_generic(const void* in, void* out, int ndim, const int64_t* dims,
+                    const int* perm, int elem, hipStream_t s);
+// out[a, c, b, p] = in[a, b, c, p] for an (A, B, C, P) column-major tensor.
+int permute_swap_mid(const void* in, void* out, int64_t A, int64_t B, int64_t C,
+                     int64_t P, int elem, hipStream_t s);
+
+}  // namespace hpt

@@ -1,0 +1,123 @@
+// Host-side state of one simulator handle: lattice topology, arena carve,
+// per-colour gate workspace and the job staging area.
+#pragma once
+#include <vector>
+#include <string>
+
+#include "../../include/hpt.h"
+#include "common.h"
+#include "linalg.h"
+#include "misc.h"
+#include "rcore.h"
+
+namespace hpt {
+
+struct SiteInfo {
+  int deg;
+  int bond[4];      // bond id of each leg, canonical U, D, L, R order
+  int nbr[4];       // neighbour site of each leg
+  int64_t cap;      // element capacity 4 * chi_max^deg
+  void* psi;        // device pointer (storage type)
+};
+
+struct BondInfo {
+  int v1, v2, colour;
+  int pos1, pos2;   // leg axis carrying the bond at v1, v2
+};
+
+// Offsets of every device buffer inside the arena (bytes), computed by the
+// memory model for a given config; `total` is hpt_required_bytes.
+struct Carve {
+  uint64_t psi_off[1024 + 1];
+  uint64_t gmsg, gmsg_hat, gmsg32, mmsg, mmsg_hat;
+  uint64_t t[3];
+  int64_t tcap;     // elements per temp
+  uint64_t part; int64_t part_cap;
+  uint64_t meas_scr; int64_t meas_scr_cap;
+  uint64_t slots; uint64_t slot_bytes; int max_colour_bonds;
+  uint64_t chol;    // CholeskyQR2 scratch
+  uint64_t small;   // scalars, bethe vectors, result arrays
+  uint64_t jobs; uint64_t jobs_bytes;
+  uint64_t total;
+};
+
+// Per-bond slot of the colour workspace (device pointers).
+struct BondSlot {
+  double* S[2][3];
+  double* Sinv[2][3];
+  float* S32[2][3];
+  float* Sinv32[2][3];
+  double* eigwork[2][3];
+  int* ncut;        // 6 ints
+  double* R[2];
+  double* Rinv[2];
+  double* B[2];
+  double* Tm[2];
+  double* tau;
+  double* G;
+  double* V;
+  double* s;
+  int* perm;
+  double* Uc;
+  double* Vc;
+  double* Mf[2];
+  double* Mp[2];
+  double* W[2];
+  float* W32[2];
+  double* z;
+  double* lam;
+};
+
+}  // namespace hpt
+
+struct hpt_sim {
+  hpt_config cfg;
+  int N, nb, centre, chi_max;
+  bool fp32;
+  int elem;
+  std::vector<hpt::SiteInfo> sites;
+  std::vector<hpt::BondInfo> bonds;
+  std::vector<std::vector<int>> colour_bonds;
+  std::vector<int> chi;
+  std::vector<std::vector<double>> lam;
+  hipStream_t stream;
+  char* arena;
+  uint64_t arena_bytes;
+  bool own_arena;
+  hpt::Carve cv;
+  double* gmsg;
+  double* gmsg_hat;
+  float* gmsg32;
+  double* mmsg;
+  double* mmsg_hat;
+  void* t[3];
+  double* part;
+  double* meas_scr;
+  std::vector<hpt::BondSlot> slots;
+  // CholeskyQR2 scratch
+  double *G1, *R1, *Ri1, *G2, *R2, *Ri2;
+  float* Ri32;
+  int* info;
+  // small device arrays
+  double* bethe_x;      // N + nb values
+  double* res;          // 8 doubles
+  double* delta;        // 2 nb
+  hpt::BondCore* cores_dev;
+  // job staging
+  char* jobs_dev;
+  char* jobs_host;      // pinned
+  uint64_t jobs_used;
+  // host pinned scratch for small D2H
+  char* hscratch;
+  uint64_t hscratch_bytes;
+  hpt::GateFactors gf;
+  double g1[4];
+  // diagnostics of the last layer
+  int step;
+  double layer_gate_err;
+  uint32_t layer_flags;
+  double layer_sfrac;
+  int gauge_sweeps;
+  double gauge_delta;
+  double bethe_norm;
+};

@@ -1,0 +1,1408 @@
+// Host engine of libhpt: memory model and arena carve, lattice topology,
+// the Trotter layer (field half-steps, 4-colour gate sweep, gauge BP) and the
+// measurement, all issued as stream-ordered launches of the HIP kernels.
+//
+// Paper: Sec. "Zero-Malloc Simulation Loop" (everything lives in one arena
+// sized once), Sec. "Trotter Decomposition" (colours), Algorithm "Gate
+// update", Sec. "Adaptive QR Decomposition", Sec. "BP Message Update",
+// Sec. "Correlation Function via Belief Propagation", implementation
+// pipeline figure (order of one time step), Table "Runtime diagnostic
+// measures".
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+
+namespace hpt {
+
+static thread_local std::string g_hip_error;
+void set_hip_error(hipError_t e, const char* what) {
+  g_hip_error = std::string(what) + ": " + hipGetErrorString(e);
+}
+
+namespace {
+
+constexpr uint64_t ALIGN = 256;
+inline uint64_t align_up(uint64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// topology (site v = x + Lx y; legs U, D, L, R; bonds: horizontal row-major,
+// then vertical row-major; colours H-even, H-odd, V-even, V-odd)
+void build_topology(const hpt_config& c, std::vector<SiteInfo>& sites, std::vector<BondInfo>& bonds) {
+  const int Lx = c.Lx, Ly = c.Ly;
+  sites.assign(Lx * Ly, SiteInfo{});
+  bonds.clear();
+  for (int y = 0; y < Ly; ++y)
+    for (int x = 0; x + 1 < Lx; ++x) bonds.push_back(BondInfo{x + Lx * y, x + 1 + Lx * y, x % 2, 0, 0});
+  for (int y = 0; y + 1 < Ly; ++y)
+    for (int x = 0; x < Lx; ++x) bonds.push_back(BondInfo{x + Lx * y, x + Lx * (y + 1), 2 + y % 2, 0, 0});
+  auto find_bond = [&](int a, int b) {
+    for (size_t i = 0; i < bonds.size(); ++i)
+      if ((bonds[i].v1 == a && bonds[i].v2 == b) || (bonds[i].v1 == b && bonds[i].v2 == a)) return (int)i;
+    return -1;
+  };
+  for (int y = 0; y < Ly; ++y)
+    for (int x = 0; x < Lx; ++x) {
+      const int v = x + Lx * y;
+      SiteInfo& s = sites[v];
+      s.deg = 0;
+      const int nx[4] = {x, x, x - 1, x + 1}, ny[4] = {y - 1, y + 1, y, y};
+      for (int l = 0; l < 4; ++l) {
+        if (nx[l] < 0 || nx[l] >= Lx || ny[l] < 0 || ny[l] >= Ly) continue;
+        const int u = nx[l] + Lx * ny[l];
+        s.bond[s.deg] = find_bond(v, u);
+        s.nbr[s.deg] = u;
+        s.deg++;
+      }
+    }
+  for (auto& b : bonds) {
+    for (int l = 0; l < sites[b.v1].deg; ++l)
+      if (sites[b.v1].nbr[l] == b.v2) b.pos1 = l;
+    for (int l = 0; l < sites[b.v2].deg; ++l)
+      if (sites[b.v2].nbr[l] == b.v1) b.pos2 = l;
+  }
+}
+
+int validate(const hpt_config* c) {
+  if (!c) return HPT_EINVAL;
+  if (c->Lx < 1 || c->Ly < 1 || (int64_t)c->Lx * c->Ly < 2 || (int64_t)c->Lx * c->Ly > 1024) return HPT_EINVAL;
+  if (!(c->dt != 0.0) || !std::isfinite(c->dt) || !std::isfinite(c->J) || !std::isfinite(c->h)) return HPT_EINVAL;
+  if (c->chi_max < 1 || c->chi_max > 256) return HPT_EINVAL;
+  const int cx = c->cx < 0 ? (c->Lx - 1) / 2 : c->cx, cy = c->cy < 0 ? (c->Ly - 1) / 2 : c->cy;
+  if (cx >= c->Lx || cy >= c->Ly) return HPT_EINVAL;
+  if (c->precision != HPT_FP64 && c->precision != HPT_FP32_MFMA) return HPT_EINVAL;
+  if (c->qr_mode != HPT_QR_ADAPTIVE && c->qr_mode != HPT_QR_HOUSEHOLDER) return HPT_EINVAL;
+  if (c->chol_min_ratio < 1 || c->chol_min_cols < 1) return HPT_EINVAL;
+  if (!(c->eps_cut >= 0.0) || !(c->eps_pinv >= 0.0)) return HPT_EINVAL;
+  if (!(c->bp_alpha > 0.0 && c->bp_alpha <= 1.0) || !(c->bp_tol > 0.0) || c->bp_max_sweeps < 1) return HPT_EINVAL;
+  if (c->meas_alpha > 1.0) return HPT_EINVAL;
+  if (c->bp_init != HPT_BP_UNIFORM && c->bp_init != HPT_BP_WARM) return HPT_EINVAL;
+  // the storage of one interior site must stay addressable with 64-bit offsets
+  // and its element count below 2^40
+  const int maxdeg = (c->Lx >= 3 && c->Ly >= 3) ? 4 : ((c->Lx >= 3 || c->Ly >= 3) ? 3 : 2);
+  if (4.0 * std::pow((double)c->chi_max, maxdeg) > 1.0e12) return HPT_EINVAL;
+  return HPT_OK;
+}
+
+struct SlotSizes {
+  uint64_t bytes;
+};
+
+// Walk the slot layout; when base != nullptr fill the pointers.
+uint64_t slot_layout(int C, bool fp32, char* base, BondSlot* sl) {
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t o = off;
+    off = align_up(off + bytes);
+    return base ? (void*)(base + o) : nullptr;
+  };
+  const uint64_t C2 = (uint64_t)C * C, n4 = 4ull * C;
+  for (int i = 0; i < 2; ++i)
+    for (int e = 0; e < 3; ++e) {
+      void* a = take(C2 * 8);
+      void* b = take(C2 * 8);
+      void* c = fp32 ? take(C2 * 4) : nullptr;
+      void* d = fp32 ? take(C2 * 4) : nullptr;
+      void* w = take(2 * C2 * 8);
+      if (sl) {
+        sl->S[i][e] = (double*)a;
+        sl->Sinv[i][e] = (double*)b;
+        sl->S32[i][e] = (float*)c;
+        sl->Sinv32[i][e] = (float*)d;
+        sl->eigwork[i][e] = (double*)w;
+      }
+    }
+  void* nc = take(64);
+  if (sl) sl->ncut = (int*)nc;
+  for (int i = 0; i < 2; ++i) {
+    void* r = take(n4 * n4 * 8);
+    void* ri = take(n4 * n4 * 8);
+    void* b = take(4 * n4 * n4 * 8);
+    void* t = take(n4 * n4 * 8);
+    void* mf = take(4 * n4 * (uint64_t)C * 8);
+    void* mp = take(n4 * n4 * 8);
+    void* w = take(n4 * n4 * 8);
+    void* w32 = fp32 ? take(n4 * n4 * 4) : nullptr;
+    if (sl) {
+      sl->R[i] = (double*)r;
+      sl->Rinv[i] = (double*)ri;
+      sl->B[i] = (double*)b;
+      sl->Tm[i] = (double*)t;
+      sl->Mf[i] = (double*)mf;
+      sl->Mp[i] = (double*)mp;
+      sl->W[i] = (double*)w;
+      sl->W32[i] = (float*)w32;
+    }
+  }
+  void* tau = take(2 * n4 * 8);
+  void* G = take(n4 * n4 * 8);
+  void* V = take(n4 * n4 * 8);
+  void* s = take(n4 * 8);
+  void* perm = take(n4 * 4);
+  void* Uc = take(n4 * (uint64_t)C * 8);
+  void* Vc = take(n4 * (uint64_t)C * 8);
+  void* z = take(n4 * 4 * 8);
+  void* lam = take((uint64_t)C * 8);
+  if (sl) {
+    sl->tau = (double*)tau;
+    sl->G = (double*)G;
+    sl->V = (double*)V;
+    sl->s = (double*)s;
+    sl->perm = (int*)perm;
+    sl->Uc = (double*)Uc;
+    sl->Vc = (double*)Vc;
+    sl->z = (double*)z;
+    sl->lam = (double*)lam;
+  }
+  return off;
+}
+
+void make_carve(const hpt_config& c, Carve& cv) {
+  std::vector<SiteInfo> sites;
+  std::vector<BondInfo> bonds;
+  build_topology(c, sites, bonds);
+  const bool fp32 = c.precision == HPT_FP32_MFMA;
+  const uint64_t E = fp32 ? 4 : 8;
+  const int C = c.chi_max;
+  const int N = (int)sites.size(), nb = (int)bonds.size();
+  uint64_t off = 0;
+  int64_t tcap = 4;
+  for (int v = 0; v < N; ++v) {
+    const int64_t cap = 4 * ipow(C, sites[v].deg);
+    tcap = std::max(tcap, cap);
+    cv.psi_off[v] = off;
+    off = align_up(off + cap * E);
+  }
+  cv.psi_off[N] = off;
+  const uint64_t C2 = (uint64_t)C * C;
+  cv.gmsg = off; off = align_up(off + 2ull * nb * C2 * 8);
+  cv.gmsg_hat = off; off = align_up(off + 2ull * nb * C2 * 8);
+  cv.gmsg32 = off; off = align_up(off + (fp32 ? 2ull * nb * C2 * 4 : 0));
+  cv.mmsg = off; off = align_up(off + 2ull * nb * C * 8);
+  cv.mmsg_hat = off; off = align_up(off + 2ull * nb * C * 8);
+  cv.tcap = tcap;
+  for (int i = 0; i < 3; ++i) {
+    cv.t[i] = off;
+    off = align_up(off + tcap * E);
+  }
+  const int64_t n4 = 4ll * C;
+  cv.part_cap = std::max<int64_t>(1 << 22, 64 * n4 * n4);
+  cv.part = off; off = align_up(off + cv.part_cap * 8);
+  const int maxdeg = std::max(1, [&] { int d = 0; for (auto& s : sites) d = std::max(d, s.deg); return d; }());
+  cv.meas_scr_cap = std::max<int64_t>(1 << 20, 4 * 4 * ipow(C, maxdeg - 1) + 64 * C);
+  cv.meas_scr = off; off = align_up(off + cv.meas_scr_cap * 8);
+  int mcb = 1;
+  for (int col = 0; col < 4; ++col) {
+    int n = 0;
+    for (auto& b : bonds) n += b.colour == col;
+    mcb = std::max(mcb, n);
+  }
+  cv.max_colour_bonds = mcb;
+  cv.slot_bytes = slot_layout(C, fp32, nullptr, nullptr);
+  cv.slots = off; off = align_up(off + cv.slot_bytes * mcb);
+  cv.chol = off; off = align_up(off + 6 * n4 * n4 * 8 + n4 * n4 * 4 + 4 * n4 * 8 + 256);
+  cv.small = off; off = align_up(off + (uint64_t)(N + nb + 64) * 8 + 2ull * nb * 8 + 16 * 8 +
+                                 (uint64_t)mcb * sizeof(BondCore));
+  cv.jobs_bytes = 4ull << 20;
+  cv.jobs = off; off = align_up(off + cv.jobs_bytes);
+  cv.total = off;
+}
+
+// ---------------------------------------------------------------------------
+// job staging: host pinned mirror -> device, bump allocation between syncs
+int sync_stream(hpt_sim* s) {
+  HPT_HIP(hipStreamSynchronize(s->stream));
+  s->jobs_used = 0;
+  return 0;
+}
+
+template <typename J>
+int stage(hpt_sim* s, const J* host, int n, J** dev) {
+  const uint64_t bytes = align_up(sizeof(J) * (uint64_t)std::max(n, 1));
+  if (s->jobs_used + bytes > s->cv.jobs_bytes) {
+    int rc = sync_stream(s);
+    if (rc) return rc;
+    if (bytes > s->cv.jobs_bytes) return HPT_ENOMEM;
+  }
+  std::memcpy(s->jobs_host + s->jobs_used, host, sizeof(J) * n);
+  HPT_HIP(hipMemcpyAsync(s->jobs_dev + s->jobs_used, s->jobs_host + s->jobs_used, sizeof(J) * n,
+                         hipMemcpyHostToDevice, s->stream));
+  *dev = (J*)(s->jobs_dev + s->jobs_used);
+  s->jobs_used += bytes;
+  return 0;
+}
+
+#define RC(x)            \
+  do {                   \
+    int _r = (x);        \
+    if (_r) return _r;   \
+  } while (0)
+
+int kres(int r) { return r == 0 ? 0 : (r == -3 ? HPT_EHIP : (r == -2 ? HPT_ENOMEM : HPT_EINVAL)); }
+#define KR(x) RC(kres(x))
+
+// ---------------------------------------------------------------------------
+// contractions through the MFMA GEMM
+
+// out[.., a, ..] = sum_b S[a, b] src[.., b, ..] on axis `axis` of a
+// column-major tensor with dims[0..nd-1]
+template <typename T>
+int mode_product(hpt_sim* s, const T* src, T* dst, const int64_t* dims, int nd, int axis, const T* S) {
+  int64_t inner = 1, outer = 1;
+  for (int i = 0; i < axis; ++i) inner *= dims[i];
+  for (int i = axis + 1; i < nd; ++i) outer *= dims[i];
+  const int n = (int)dims[axis];
+  GemmDesc<T> d{};
+  if (inner == 1) {
+    d.M = n; d.N = (int)outer; d.K = n; d.R = 1; d.Z = 1;
+    d.A = S; d.lda = n; d.tA = 0;
+    d.B = src; d.ldb = n; d.tB = 0;
+    d.C = dst; d.ldc = n; d.c_double = 0;
+  } else {
+    d.M = (int)inner; d.N = n; d.K = n; d.R = 1; d.Z = (int)outer;
+    d.A = src; d.lda = inner; d.sAz = inner * n; d.tA = 0;
+    d.B = S; d.ldb = n; d.sBz = 0; d.tB = 1;
+    d.C = dst; d.ldc = inner; d.sCz = inner * n; d.c_double = 0;
+  }
+  d.alpha = 1.0; d.beta = 0.0;
+  KR(gemm<T>(d, s->part, s->cv.part_cap, s->stream));
+  return 0;
+}
+
+// out[a, a'] = sum over every other index of psi[.., a, ..] cur[.., a', ..]
+template <typename T>
+int leg_gram(hpt_sim* s, const T* psi, const T* cur, const int64_t* dims, int nd, int axis, double* out) {
+  int64_t inner = 1, outer = 1;
+  for (int i = 0; i < axis; ++i) inner *= dims[i];
+  for (int i = axis + 1; i < nd; ++i) outer *= dims[i];
+  const int n = (int)dims[axis];
+  GemmDesc<T> d{};
+  if (inner == 1) {
+    d.M = n; d.N = n; d.K = (int)outer; d.R = 1; d.Z = 1;
+    d.A = psi; d.lda = n; d.tA = 0;
+    d.B = cur; d.ldb = n; d.tB = 1;
+  } else {
+    d.M = n; d.N = n; d.K = (int)inner; d.R = (int)outer; d.Z = 1;
+    d.A = psi; d.lda = inner; d.sAr = inner * n; d.tA = 1;
+    d.B = cur; d.ldb = inner; d.sBr = inner * n; d.tB = 0;
+  }
+  d.C = out; d.ldc = n; d.c_double = 1;
+  d.alpha = 1.0; d.beta = 0.0;
+  KR(gemm<T>(d, s->part, s->cv.part_cap, s->stream));
+  return 0;
+}
+
+// C (m x n, double or T) = A (m x k) * B (k x n), plain column-major
+template <typename T>
+int matmul(hpt_sim* s, int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, int tA, const T* B,
+           int64_t ldb, int tB, void* C, int64_t ldc, int c_double) {
+  GemmDesc<T> d{};
+  d.M = (int)m; d.N = (int)n; d.K = (int)k; d.R = 1; d.Z = 1;
+  d.A = A; d.lda = lda; d.tA = tA;
+  d.B = B; d.ldb = ldb; d.tB = tB;
+  d.C = C; d.ldc = ldc; d.c_double = c_double;
+  d.alpha = 1.0; d.beta = 0.0;
+  KR(gemm<T>(d, s->part, s->cv.part_cap, s->stream));
+  return 0;
+}
+
+template <typename T> T* psi_of(hpt_sim* s, int v) { return (T*)s->sites[v].psi; }
+
+void site_dims(hpt_sim* s, int v, int64_t* dims) {
+  const SiteInfo& si = s->sites[v];
+  for (int l = 0; l < si.deg; ++l) dims[l] = s->chi[si.bond[l]];
+  dims[si.deg] = 4;
+}
+
+double* gmsg_slot(hpt_sim* s, int b, int dir) {
+  return s->gmsg + (uint64_t)(2 * b + dir) * s->chi_max * s->chi_max;
+}
+double* gmsg_hat_slot(hpt_sim* s, int b, int dir) {
+  return s->gmsg_hat + (uint64_t)(2 * b + dir) * s->chi_max * s->chi_max;
+}
+float* gmsg32_slot(hpt_sim* s, int b, int dir) {
+  return s->gmsg32 + (uint64_t)(2 * b + dir) * s->chi_max * s->chi_max;
+}
+double* mmsg_slot(hpt_sim* s, int b, int dir) { return s->mmsg + (uint64_t)(2 * b + dir) * s->chi_max; }
+double* mmsg_hat_slot(hpt_sim* s, int b, int dir) { return s->mmsg_hat + (uint64_t)(2 * b + dir) * s->chi_max; }
+// direction index of the message leaving `src` along bond b
+int dir_from(hpt_sim* s, int b, int src) { return s->bonds[b].v1 == src ? 0 : 1; }
+
+// ---------------------------------------------------------------------------
+// row a1: field half-step
+template <typename T>
+int apply_field_t(hpt_sim* s) {
+  for (int v = 0; v < s->N; ++v) {
+    int64_t dims[5];
+    site_dims(s, v, dims);
+    int64_t slice = 1;
+    for (int l = 0; l < s->sites[v].deg; ++l) slice *= dims[l];
+    KR(launch_field<T>(psi_of<T>(s, v), slice, s->g1[0], s->g1[1], s->g1[2], s->g1[3], s->stream));
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// rows a2..a7: gate update of every bond of one colour
+struct SitePlan {
+  int v, cut, deg;
+  int64_t dims[5];
+  int nenv;
+  int env_pos[3];
+  int64_t m, n;
+  int chol;
+  int k;
+};
+
+template <typename T>
+const T* env_S(BondSlot& sl, int i, int e, bool inv);
+template <>
+const double* env_S<double>(BondSlot& sl, int i, int e, bool inv) { return inv ? sl.Sinv[i][e] : sl.S[i][e]; }
+template <>
+const float* env_S<float>(BondSlot& sl, int i, int e, bool inv) { return inv ? sl.Sinv32[i][e] : sl.S32[i][e]; }
+
+template <typename T>
+int phase_a_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, uint32_t& flags) {
+  const BondInfo& bi = s->bonds[b];
+  const T* S_unused = nullptr;
+  (void)S_unused;
+  T* psi = psi_of<T>(s, P.v);
+  // absorb sqrt of each environment message (mode products, ping-pong)
+  int64_t dims[5];
+  for (int l = 0; l <= P.deg; ++l) dims[l] = P.dims[l];
+  const T* src = psi;
+  int ti = 0;
+  const bool need_perm = P.cut != P.deg - 1;
+  for (int e = 0; e < P.nenv; ++e) {
+    const bool last = e == P.nenv - 1;
+    T* dst;
+    if (last && !need_perm && src != psi)
+      dst = psi;
+    else {
+      dst = (T*)s->t[ti];
+      ti ^= 1;
+    }
+    RC(mode_product<T>(s, src, dst, dims, P.deg + 1, P.env_pos[e], env_S<T>(sl, i, e, false)));
+    src = dst;
+  }
+  // permute [A, cut, C, P] -> [A, C, cut, P] into the site's own storage
+  if (need_perm) {
+    int64_t A = 1, Cc = 1;
+    for (int l = 0; l < P.cut; ++l) A *= dims[l];
+    for (int l = P.cut + 1; l < P.deg; ++l) Cc *= dims[l];
+    T* dst = psi;
+    if (src == psi) {  // no environment legs were absorbed: permute via a temp
+      HPT_HIP(hipMemcpyAsync(s->t[0], psi, sizeof(T) * P.m * P.n, hipMemcpyDeviceToDevice, s->stream));
+      src = (T*)s->t[0];
+    }
+    KR(permute_swap_mid(src, dst, A, dims[P.cut], Cc, 4, (int)sizeof(T), s->stream));
+  } else if (src != psi) {
+    HPT_HIP(hipMemcpyAsync(psi, src, sizeof(T) * P.m * P.n, hipMemcpyDeviceToDevice, s->stream));
+  }
+  // QR of X (m x n) held in psi's storage
+  const int n = (int)P.n;
+  const int64_t m = P.m;
+  const int ldR = 4 * s->chi_max;
+  P.chol = 0;
+  bool use_chol = s->cfg.qr_mode == HPT_QR_ADAPTIVE && m >= (int64_t)s->cfg.chol_min_ratio * n &&
+                  n >= s->cfg.chol_min_cols;
+  if (use_chol) {
+    // CholeskyQR2: G1 = X^T X, R1 = chol(G1), Q1 = X R1^{-1}, G2 = Q1^T Q1, R2 = chol(G2)
+    RC(matmul<T>(s, n, n, m, psi, m, 1, psi, m, 0, s->G1, n, 1));
+    CholJob cj{s->G1, n, n, s->R1, n, s->info, nullptr};
+    CholJob* cjd;
+    RC(stage(s, &cj, 1, &cjd));
+    KR(launch_cholesky(cjd, 1, 1e-13, s->stream));
+    int info = 0;
+    HPT_HIP(hipMemcpyAsync(s->hscratch, s->info, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    RC(sync_stream(s));
+    std::memcpy(&info, s->hscratch, sizeof(int));
+    if (info == 0) {
+      TriInvJob tj{s->R1, n, n, s->Ri1, n, nullptr};
+      TriInvJob* tjd;
+      RC(stage(s, &tj, 1, &tjd));
+      KR(launch_tri_inverse(tjd, 1, s->stream));
+      const T* Ri;
+      if (sizeof(T) == 4) {
+        KR(launch_d2f(s->Ri1, s->Ri32, (int64_t)n * n, s->stream));
+        Ri = (const T*)s->Ri32;
+      } else {
+        Ri = (const T*)s->Ri1;
+      }
+      T* Q1 = (T*)s->t[0];
+      RC(matmul<T>(s, m, n, n, psi, m, 0, Ri, n, 0, Q1, m, 0));
+      RC(matmul<T>(s, n, n, m, Q1, m, 1, Q1, m, 0, s->G2, n, 1));
+      CholJob cj2{s->G2, n, n, s->R2, n, s->info, nullptr};
+      RC(stage(s, &cj2, 1, &cjd));
+      KR(launch_cholesky(cjd, 1, 1e-13, s->stream));
+      HPT_HIP(hipMemcpyAsync(s->hscratch, s->info, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+      RC(sync_stream(s));
+      std::memcpy(&info, s->hscratch, sizeof(int));
+      if (info == 0) {
+        TriInvJob tj2{s->R2, n, n, s->Ri2, n, nullptr};
+        RC(stage(s, &tj2, 1, &tjd));
+        KR(launch_tri_inverse(tjd, 1, s->stream));
+        // R = R2 R1 (ld 4 chi_max), Rinv = R1^{-1} R2^{-1}
+        SmallGemmJob gj[2];
+        std::memset(gj, 0, sizeof(gj));
+        gj[0] = SmallGemmJob{n, n, n, nullptr, nullptr, nullptr, s->R2, n, 0, s->R1, n, 0, sl.R[i], ldR, 1.0, 0.0, nullptr};
+        gj[1] = SmallGemmJob{n, n, n, nullptr, nullptr, nullptr, s->Ri1, n, 0, s->Ri2, n, 0, sl.Rinv[i], ldR, 1.0, 0.0, nullptr};
+        SmallGemmJob* gjd;
+        RC(stage(s, gj, 2, &gjd));
+        KR(launch_small_gemm(gjd, 2, s->stream));
+        P.chol = 1;
+        P.k = n;
+      }
+    }
+    if (!P.chol) flags |= HPT_FLAG_QR_FALLBACK;
+  }
+  if (!P.chol) {
+    if (std::min<int64_t>(m, n) > 1024) return HPT_EINVAL;
+    QrJob<T> qj{psi, m, (int)m, n, sl.R[i], ldR, s->R1 /* tau scratch */, 1, nullptr};
+    QrJob<T>* qjd;
+    RC(stage(s, &qj, 1, &qjd));
+    KR(launch_householder<T>(qjd, 1, s->stream));
+    P.k = (int)std::min<int64_t>(m, n);
+  }
+  if (i == 0) {
+    const int ncols = P.chol ? n : P.k;
+    KR(launch_sign_projection<T>(psi, m, m, ncols, sl.z, s->part, s->cv.part_cap, s->stream));
+  }
+  (void)bi;
+  return 0;
+}
+
+template <typename T>
+int phase_c_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, int cn) {
+  T* psi = psi_of<T>(s, P.v);
+  const int nS = P.chol ? (int)P.n : P.k;
+  const int n4 = 4 * cn;
+  const T* W;
+  if (sizeof(T) == 4) {
+    KR(launch_d2f(sl.W[i], sl.W32[i], (int64_t)nS * n4, s->stream));
+    W = (const T*)sl.W32[i];
+  } else {
+    W = (const T*)sl.W[i];
+  }
+  T* out = (T*)s->t[0];
+  RC(matmul<T>(s, P.m, n4, nS, psi, P.m, 0, W, nS, 0, out, P.m, 0));
+  // new dims
+  int64_t dims[5];
+  for (int l = 0; l <= P.deg; ++l) dims[l] = P.dims[l];
+  dims[P.cut] = cn;
+  const T* src = out;
+  int ti = 1;
+  if (P.cut != P.deg - 1) {
+    int64_t A = 1, Cc = 1;
+    for (int l = 0; l < P.cut; ++l) A *= dims[l];
+    for (int l = P.cut + 1; l < P.deg; ++l) Cc *= dims[l];
+    T* dst = (T*)s->t[1];
+    KR(permute_swap_mid(src, dst, A, Cc, cn, 4, (int)sizeof(T), s->stream));
+    src = dst;
+    ti = 0;
+  }
+  // deabsorb with the pseudo-inverse square roots; the last product lands in psi
+  for (int e = 0; e < P.nenv; ++e) {
+    const bool last = e == P.nenv - 1;
+    T* dst = last ? psi : (T*)s->t[ti];
+    RC(mode_product<T>(s, src, dst, dims, P.deg + 1, P.env_pos[e], env_S<T>(sl, i, e, true)));
+    if (!last) {
+      src = dst;
+      ti ^= 1;
+    }
+  }
+  if (P.nenv == 0) {
+    int64_t total = 4;
+    for (int l = 0; l < P.deg; ++l) total *= dims[l];
+    HPT_HIP(hipMemcpyAsync(psi, src, sizeof(T) * total, hipMemcpyDeviceToDevice, s->stream));
+  }
+  (void)b;
+  return 0;
+}
+
+template <typename T>
+int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
+  const int nb = (int)cbonds.size();
+  if (nb == 0) return 0;
+  if (nb > s->cv.max_colour_bonds) return HPT_EINVAL;
+  std::vector<SitePlan> plans(2 * nb);
+  uint32_t flags = 0;
+  // environment pseudo square roots of every site in the colour
+  std::vector<PsqJob> pj;
+  for (int q = 0; q < nb; ++q) {
+    const int b = cbonds[q];
+    BondSlot& sl = s->slots[q];
+    for (int i = 0; i < 2; ++i) {
+      SitePlan& P = plans[2 * q + i];
+      P.v = i == 0 ? s->bonds[b].v1 : s->bonds[b].v2;
+      P.cut = i == 0 ? s->bonds[b].pos1 : s->bonds[b].pos2;
+      P.deg = s->sites[P.v].deg;
+      site_dims(s, P.v, P.dims);
+      P.nenv = 0;
+      P.m = 1;
+      for (int l = 0; l < P.deg; ++l) {
+        if (l == P.cut) continue;
+        const int be = s->sites[P.v].bond[l];
+        const int u = s->sites[P.v].nbr[l];
+        const int ch = s->chi[be];
+        PsqJob j{gmsg_slot(s, be, dir_from(s, be, u)), sl.S[i][P.nenv], sl.Sinv[i][P.nenv],
+                 s->fp32 ? sl.S32[i][P.nenv] : nullptr, s->fp32 ? sl.Sinv32[i][P.nenv] : nullptr,
+                 sl.eigwork[i][P.nenv], ch, sl.ncut + 3 * i + P.nenv};
+        pj.push_back(j);
+        P.env_pos[P.nenv++] = l;
+        P.m *= ch;
+      }
+      P.n = 4ll * s->chi[b];
+    }
+  }
+  if (!pj.empty()) {
+    PsqJob* pjd;
+    RC(stage(s, pj.data(), (int)pj.size(), &pjd));
+    KR(launch_pseudo_sqrt(pjd, (int)pj.size(), s->cfg.eps_pinv, s->stream));
+  }
+  // phase A: absorb, permute, QR
+  for (int q = 0; q < nb; ++q)
+    for (int i = 0; i < 2; ++i) RC(phase_a_site<T>(s, cbonds[q], i, s->slots[q], plans[2 * q + i], flags));
+  // phase B: R-core of every bond of the colour
+  std::vector<BondCore> cores(nb);
+  const int C = s->chi_max, ldR = 4 * C;
+  for (int q = 0; q < nb; ++q) {
+    const int b = cbonds[q];
+    BondSlot& sl = s->slots[q];
+    BondCore& bc = cores[q];
+    std::memset(&bc, 0, sizeof(bc));
+    bc.chi_cut = s->chi[b];
+    for (int i = 0; i < 2; ++i) {
+      const SitePlan& P = plans[2 * q + i];
+      bc.k[i] = P.k;
+      bc.q[i] = std::min(4 * P.k, 4 * bc.chi_cut);
+      bc.chol[i] = P.chol;
+      bc.R[i] = sl.R[i];
+      bc.Rinv[i] = sl.Rinv[i];
+      bc.B[i] = sl.B[i];
+      bc.Tm[i] = sl.Tm[i];
+      bc.Mf[i] = sl.Mf[i];
+      bc.Mp[i] = sl.Mp[i];
+      bc.W[i] = sl.W[i];
+      bc.msg[i] = gmsg_slot(s, b, i);
+    }
+    bc.chi_max = C;
+    bc.eps_cut = s->cfg.eps_cut;
+    bc.ldR = ldR;
+    bc.ldT = ldR;
+    bc.tau = sl.tau;
+    bc.G = sl.G;
+    bc.ldG = ldR;
+    bc.V = sl.V;
+    bc.s = sl.s;
+    bc.perm = sl.perm;
+    bc.Uc = sl.Uc;
+    bc.Vc = sl.Vc;
+    bc.z = sl.z;
+    bc.lam = sl.lam;
+  }
+  // stage the records through the pinned scratch; it is next written by the
+  // device-to-host copy at the end of this phase, which is stream-ordered after
+  BondCore* cd = s->cores_dev;
+  std::memcpy(s->hscratch, cores.data(), sizeof(BondCore) * nb);
+  HPT_HIP(hipMemcpyAsync(cd, s->hscratch, sizeof(BondCore) * nb, hipMemcpyHostToDevice, s->stream));
+  KR(launch_rcore_build_B(cd, nb, s->gf, s->stream));
+  {
+    std::vector<QrJob<double>> qj;
+    for (int q = 0; q < nb; ++q)
+      for (int i = 0; i < 2; ++i) {
+        const BondCore& bc = cores[q];
+        qj.push_back(QrJob<double>{bc.B[i], 4 * bc.k[i], 4 * bc.k[i], 4 * bc.chi_cut, bc.Tm[i], ldR,
+                                   s->slots[q].tau + i * 4 * C, 1, nullptr});
+      }
+    QrJob<double>* qd;
+    RC(stage(s, qj.data(), (int)qj.size(), &qd));
+    KR(launch_householder<double>(qd, (int)qj.size(), s->stream));
+  }
+  {
+    std::vector<SmallGemmJob> gj;
+    std::vector<SvdJob> sj;
+    for (int q = 0; q < nb; ++q) {
+      const BondCore& bc = cores[q];
+      const int q0 = bc.q[0], q1 = bc.q[1], K = 4 * bc.chi_cut;
+      SmallGemmJob j;
+      std::memset(&j, 0, sizeof(j));
+      if (q0 >= q1)
+        j = SmallGemmJob{q0, q1, K, nullptr, nullptr, nullptr, bc.Tm[0], ldR, 0, bc.Tm[1], ldR, 1, bc.G, ldR, 1.0, 0.0, nullptr};
+      else
+        j = SmallGemmJob{q1, q0, K, nullptr, nullptr, nullptr, bc.Tm[1], ldR, 0, bc.Tm[0], ldR, 1, bc.G, ldR, 1.0, 0.0, nullptr};
+      gj.push_back(j);
+      sj.push_back(SvdJob{bc.G, ldR, std::max(q0, q1), std::min(q0, q1), bc.V, ldR, bc.s, bc.perm, nullptr});
+    }
+    SmallGemmJob* gd;
+    RC(stage(s, gj.data(), nb, &gd));
+    KR(launch_small_gemm(gd, nb, s->stream));
+    SvdJob* sd;
+    RC(stage(s, sj.data(), nb, &sd));
+    KR(launch_jacobi_svd(sd, nb, s->stream));
+  }
+  KR(launch_rcore_select(cd, nb, s->stream));
+  {
+    std::vector<SmallGemmJob> gj;
+    for (int q = 0; q < nb; ++q) {
+      const BondCore& bc = cores[q];
+      for (int i = 0; i < 2; ++i) {
+        SmallGemmJob j{4 * bc.k[i], 0, bc.q[i], nullptr, &cd[q].chi_new, nullptr, bc.B[i], 4 * bc.k[i], 0,
+                       i == 0 ? bc.Uc : bc.Vc, ldR, 0, bc.Mf[i], 4 * bc.k[i], 1.0, 0.0, nullptr};
+        gj.push_back(j);
+      }
+    }
+    SmallGemmJob* gd;
+    RC(stage(s, gj.data(), (int)gj.size(), &gd));
+    KR(launch_small_gemm(gd, (int)gj.size(), s->stream));
+  }
+  KR(launch_rcore_rearrange(cd, nb, s->stream));
+  {
+    std::vector<SmallGemmJob> gj;
+    for (int q = 0; q < nb; ++q) {
+      const BondCore& bc = cores[q];
+      for (int i = 0; i < 2; ++i) {
+        if (!bc.chol[i]) continue;
+        const int n = 4 * bc.chi_cut;
+        SmallGemmJob j{n, 0, n, nullptr, &cd[q].n4, nullptr, bc.Rinv[i], ldR, 0, bc.Mp[i], bc.k[i], 0,
+                       bc.W[i], n, 1.0, 0.0, nullptr};
+        gj.push_back(j);
+      }
+    }
+    if (!gj.empty()) {
+      SmallGemmJob* gd;
+      RC(stage(s, gj.data(), (int)gj.size(), &gd));
+      KR(launch_small_gemm(gd, (int)gj.size(), s->stream));
+    }
+  }
+  KR(launch_rcore_signs(cd, nb, s->stream));
+  // bring back chi_new, status, gate_err, flags and lambda
+  const uint64_t core_bytes = sizeof(BondCore) * nb;
+  HPT_HIP(hipMemcpyAsync(s->hscratch, cd, core_bytes, hipMemcpyDeviceToHost, s->stream));
+  const uint64_t lam_off = align_up(core_bytes);
+  for (int q = 0; q < nb; ++q)
+    HPT_HIP(hipMemcpyAsync(s->hscratch + lam_off + (uint64_t)q * C * 8, s->slots[q].lam, C * 8,
+                           hipMemcpyDeviceToHost, s->stream));
+  int ncut_off = (int)(lam_off + (uint64_t)nb * C * 8);
+  for (int q = 0; q < nb; ++q)
+    HPT_HIP(hipMemcpyAsync(s->hscratch + ncut_off + q * 64, s->slots[q].ncut, 6 * sizeof(int),
+                           hipMemcpyDeviceToHost, s->stream));
+  RC(sync_stream(s));
+  std::memcpy(cores.data(), s->hscratch, core_bytes);
+  for (int q = 0; q < nb; ++q) {
+    const int b = cbonds[q];
+    const BondCore& bc = cores[q];
+    if (bc.status != 0) return HPT_ENUMERIC;
+    if (!std::isfinite(bc.gate_err)) return HPT_ENUMERIC;
+    const int* nc = (const int*)(s->hscratch + ncut_off + q * 64);
+    for (int i = 0; i < 2; ++i)
+      for (int e = 0; e < plans[2 * q + i].nenv; ++e) {
+        if (nc[3 * i + e] < 0) return HPT_ENUMERIC;
+        if (nc[3 * i + e] > 0) flags |= HPT_FLAG_PINV_CUT;
+      }
+    flags |= (uint32_t)bc.flags;
+    s->layer_gate_err += bc.gate_err;
+    s->lam[b].assign((const double*)(s->hscratch + lam_off + (uint64_t)q * C * 8),
+                     (const double*)(s->hscratch + lam_off + (uint64_t)q * C * 8) + bc.chi_new);
+  }
+  // phase C: reconstruct, inverse permute, deabsorb
+  for (int q = 0; q < nb; ++q)
+    for (int i = 0; i < 2; ++i)
+      RC(phase_c_site<T>(s, cbonds[q], i, s->slots[q], plans[2 * q + i], cores[q].chi_new));
+  for (int q = 0; q < nb; ++q) s->chi[cbonds[q]] = cores[q].chi_new;
+  s->layer_flags |= flags;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// row a8: gauge BP on the norm network
+
+template <typename T>
+const T* gmsg_T(hpt_sim* s, int b, int dir);
+template <>
+const double* gmsg_T<double>(hpt_sim* s, int b, int dir) { return gmsg_slot(s, b, dir); }
+template <>
+const float* gmsg_T<float>(hpt_sim* s, int b, int dir) { return gmsg32_slot(s, b, dir); }
+
+// leave-one-out products: messages applied on every leg except the output one
+template <typename T>
+int loo(hpt_sim* s, int v, const T* cur, const std::vector<int>& rem, const int64_t* dims, int nd,
+        int busy_mask) {
+  const SiteInfo& si = s->sites[v];
+  const T* psi = psi_of<T>(s, v);
+  if (rem.size() == 1) {
+    const int l = rem[0];
+    const int b = si.bond[l];
+    return leg_gram<T>(s, psi, cur, dims, nd, l, gmsg_hat_slot(s, b, dir_from(s, b, v)));
+  }
+  const size_t h = rem.size() / 2;
+  std::vector<int> H1(rem.begin(), rem.begin() + h), H2(rem.begin() + h, rem.end());
+  for (int pass = 0; pass < 2; ++pass) {
+    const std::vector<int>& apply = pass == 0 ? H2 : H1;
+    const std::vector<int>& keep = pass == 0 ? H1 : H2;
+    const T* src = cur;
+    int mask = busy_mask;
+    int last_t = -1;
+    for (size_t a = 0; a < apply.size(); ++a) {
+      int ti = -1;
+      for (int k = 0; k < 3; ++k)
+        if (!(mask & (1 << k))) { ti = k; break; }
+      if (ti < 0) return HPT_EINVAL;
+      T* dst = (T*)s->t[ti];
+      const int l = apply[a];
+      const int b = si.bond[l];
+      RC(mode_product<T>(s, src, dst, dims, nd, l, gmsg_T<T>(s, b, dir_from(s, b, si.nbr[l]))));
+      if (last_t >= 0) mask &= ~(1 << last_t);
+      mask |= 1 << ti;
+      last_t = ti;
+      src = dst;
+    }
+    RC(loo<T>(s, v, src, keep, dims, nd, mask));
+  }
+  return 0;
+}
+
+template <typename T>
+int gauge_bp_t(hpt_sim* s, int init, int* sweeps_out, double* delta_out) {
+  const int nbd = 2 * s->nb;
+  if (init == HPT_BP_UNIFORM) {
+    for (int b = 0; b < s->nb; ++b)
+      for (int d = 0; d < 2; ++d)
+        KR(launch_fill_identity(gmsg_slot(s, b, d), s->chi[b], 1.0 / std::sqrt((double)s->chi[b]), s->stream));
+  }
+  std::vector<GaugeNormJob> nj(nbd);
+  for (int b = 0; b < s->nb; ++b)
+    for (int d = 0; d < 2; ++d) nj[2 * b + d] = GaugeNormJob{gmsg_slot(s, b, d), gmsg_hat_slot(s, b, d), s->chi[b]};
+  std::vector<DotJob> dj;
+  for (int v = 0; v < s->N; ++v) {
+    const int b = s->sites[v].bond[0];
+    const int u = s->sites[v].nbr[0];
+    const int64_t c2 = (int64_t)s->chi[b] * s->chi[b];
+    dj.push_back(DotJob{gmsg_hat_slot(s, b, dir_from(s, b, v)), gmsg_slot(s, b, dir_from(s, b, u)), c2, s->bethe_x + v});
+  }
+  for (int b = 0; b < s->nb; ++b) {
+    const int64_t c2 = (int64_t)s->chi[b] * s->chi[b];
+    dj.push_back(DotJob{gmsg_slot(s, b, 0), gmsg_slot(s, b, 1), c2, s->bethe_x + s->N + b});
+  }
+  int sweeps = 0;
+  double delta = INFINITY;
+  double res[5] = {0, 1, 0, 0, 0};
+  const int maxs = s->cfg.bp_max_sweeps;
+  while (sweeps < maxs) {
+    if (s->fp32) KR(launch_d2f(s->gmsg, s->gmsg32, (int64_t)nbd * s->chi_max * s->chi_max, s->stream));
+    for (int v = 0; v < s->N; ++v) {
+      int64_t dims[5];
+      site_dims(s, v, dims);
+      std::vector<int> rem;
+      for (int l = 0; l < s->sites[v].deg; ++l) rem.push_back(l);
+      RC(loo<T>(s, v, psi_of<T>(s, v), rem, dims, s->sites[v].deg + 1, 0));
+    }
+    DotJob* djd;
+    RC(stage(s, dj.data(), (int)dj.size(), &djd));
+    KR(launch_dots(djd, (int)dj.size(), s->stream));
+    GaugeNormJob* njd;
+    RC(stage(s, nj.data(), nbd, &njd));
+    KR(launch_gauge_norm(njd, nbd, s->cfg.bp_alpha, s->delta, s->stream));
+    KR(launch_log_product(s->bethe_x, s->N, s->nb, s->delta, nbd, s->res, s->stream));
+    HPT_HIP(hipMemcpyAsync(s->hscratch, s->res, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    RC(sync_stream(s));
+    std::memcpy(res, s->hscratch, sizeof(res));
+    delta = res[4];
+    ++sweeps;
+    if (!std::isfinite(delta)) return HPT_ENUMERIC;
+    if (delta < s->cfg.bp_tol) break;
+  }
+  if (res[2] != 0.0)
+    s->bethe_norm = 0.0;
+  else if (res[3] != 0.0)
+    s->bethe_norm = NAN;
+  else
+    s->bethe_norm = res[1] * std::exp(res[0]);
+  s->gauge_sweeps = sweeps;
+  s->gauge_delta = delta;
+  if (sweeps_out) *sweeps_out = sweeps;
+  if (delta_out) *delta_out = delta;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// row a9: measurement BP and the log-space Bethe sum
+
+template <typename T>
+int meas_outgoing(hpt_sim* s, bool only_first_leg) {
+  // jobs for every (site, leg), batched within the scratch and partial budgets
+  std::vector<MeasJob> batch;
+  int64_t used = 0, max_stride = 1;
+  auto flush = [&]() -> int {
+    if (batch.empty()) return 0;
+    MeasJob* jd;
+    RC(stage(s, batch.data(), (int)batch.size(), &jd));
+    const int r = meas_contract(jd, batch.data(), (int)batch.size(), s->fp32 ? 0 : 1, s->part, s->cv.part_cap, s->stream);
+    if (r == -2) return HPT_ENOMEM;
+    KR(r);
+    batch.clear();
+    used = 0;
+    return 0;
+  };
+  for (int v = 0; v < s->N; ++v) {
+    const SiteInfo& si = s->sites[v];
+    int64_t dims[5];
+    site_dims(s, v, dims);
+    int64_t slice = 1;
+    for (int l = 0; l < si.deg; ++l) slice *= dims[l];
+    const int p = v == s->centre ? 3 : 0;
+    const T* Tv = psi_of<T>(s, v) + (int64_t)p * slice;
+    for (int k = 0; k < si.deg; ++k) {
+      if (only_first_leg && k > 0) break;
+      MeasJob j;
+      std::memset(&j, 0, sizeof(j));
+      j.T = Tv;
+      j.I = 1;
+      j.O = 1;
+      for (int l = 0; l < k; ++l) {
+        j.I *= dims[l];
+        const int b = si.bond[l];
+        j.xm[j.nx] = mmsg_slot(s, b, dir_from(s, b, si.nbr[l]));
+        j.xd[j.nx++] = (int)dims[l];
+      }
+      for (int l = k + 1; l < si.deg; ++l) {
+        j.O *= dims[l];
+        const int b = si.bond[l];
+        j.ym[j.ny] = mmsg_slot(s, b, dir_from(s, b, si.nbr[l]));
+        j.yd[j.ny++] = (int)dims[l];
+      }
+      j.nk = dims[k];
+      const int bk = si.bond[k];
+      j.out = mmsg_hat_slot(s, bk, dir_from(s, bk, v));
+      const int64_t need = j.I + j.O + (j.O > 1 ? j.I * j.nk : 0);
+      // per-job stride of the partial buffer in meas_contract
+      const int64_t stride = std::max<int64_t>(j.O > 1 ? ceil_div(j.O, 256) * j.I * j.nk : 1,
+                                               ceil_div(j.I, 64 * 256) * j.nk);
+      if (need > s->cv.meas_scr_cap || stride > s->cv.part_cap) return HPT_ENOMEM;
+      const int64_t new_stride = std::max(max_stride, stride);
+      if (used + need > s->cv.meas_scr_cap || new_stride * (int64_t)(batch.size() + 1) > s->cv.part_cap ||
+          batch.size() >= 4096) {
+        RC(flush());
+        max_stride = stride;
+      } else {
+        max_stride = new_stride;
+      }
+      j.x = s->meas_scr + used;
+      j.y = j.x + j.I;
+      j.S = j.y + j.O;
+      used += need;
+      batch.push_back(j);
+    }
+  }
+  return flush();
+}
+
+template <typename T>
+int measure_t(hpt_sim* s, hpt_measurement* out) {
+  const int nbd = 2 * s->nb;
+  for (int b = 0; b < s->nb; ++b)
+    for (int d = 0; d < 2; ++d)
+      KR(launch_fill_value(mmsg_slot(s, b, d), s->chi[b], 1.0 / std::sqrt((double)s->chi[b]), s->stream));
+  std::vector<MeasNormJob> nj(nbd);
+  for (int b = 0; b < s->nb; ++b)
+    for (int d = 0; d < 2; ++d) nj[2 * b + d] = MeasNormJob{mmsg_slot(s, b, d), mmsg_hat_slot(s, b, d), s->chi[b]};
+  const double alpha = s->cfg.meas_alpha > 0.0 ? s->cfg.meas_alpha : s->cfg.bp_alpha;
+  const double tol = s->cfg.meas_tol > 0.0 ? s->cfg.meas_tol : s->cfg.bp_tol;
+  const int maxs = s->cfg.meas_max_sweeps > 0 ? s->cfg.meas_max_sweeps : s->cfg.bp_max_sweeps;
+  int sweeps = 0;
+  double delta = INFINITY;
+  double res[5];
+  while (sweeps < maxs) {
+    RC(meas_outgoing<T>(s, false));
+    MeasNormJob* njd;
+    RC(stage(s, nj.data(), nbd, &njd));
+    KR(launch_meas_norm(njd, nbd, alpha, s->delta, s->stream));
+    KR(launch_log_product(s->bethe_x, 0, 0, s->delta, nbd, s->res, s->stream));
+    HPT_HIP(hipMemcpyAsync(s->hscratch, s->res, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    RC(sync_stream(s));
+    std::memcpy(res, s->hscratch, sizeof(res));
+    delta = res[4];
+    ++sweeps;
+    if (!std::isfinite(delta)) return HPT_ENUMERIC;
+    if (delta < tol) break;
+  }
+  // Bethe: vs_v = <out_{v -> leg0}, m_{leg0 -> v}>, Z_e = <m_{b,0}, m_{b,1}>
+  RC(meas_outgoing<T>(s, true));
+  std::vector<DotJob> dj;
+  for (int v = 0; v < s->N; ++v) {
+    const int b = s->sites[v].bond[0];
+    const int u = s->sites[v].nbr[0];
+    dj.push_back(DotJob{mmsg_hat_slot(s, b, dir_from(s, b, v)), mmsg_slot(s, b, dir_from(s, b, u)), s->chi[b], s->bethe_x + v});
+  }
+  for (int b = 0; b < s->nb; ++b) dj.push_back(DotJob{mmsg_slot(s, b, 0), mmsg_slot(s, b, 1), s->chi[b], s->bethe_x + s->N + b});
+  DotJob* djd;
+  RC(stage(s, dj.data(), (int)dj.size(), &djd));
+  KR(launch_dots(djd, (int)dj.size(), s->stream));
+  KR(launch_log_product(s->bethe_x, s->N, s->nb, nullptr, 0, s->res, s->stream));
+  HPT_HIP(hipMemcpyAsync(s->hscratch, s->res, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  RC(sync_stream(s));
+  std::memcpy(res, s->hscratch, sizeof(res));
+  uint32_t flags = s->layer_flags;
+  double C, logC;
+  int sign;
+  if (res[2] != 0.0) {
+    C = 0.0; logC = -INFINITY; sign = 0; flags |= HPT_FLAG_BETHE_ZERO;
+  } else if (res[3] != 0.0) {
+    C = NAN; logC = NAN; sign = 0; flags |= HPT_FLAG_BETHE_ZERO;
+  } else {
+    logC = res[0]; sign = res[1] < 0 ? -1 : 1; C = sign * std::exp(logC);
+  }
+  if (delta >= tol) flags |= HPT_FLAG_BP_NOT_CONVERGED_MEAS;
+  if (sweeps >= s->cfg.trap_sweeps && delta < tol) flags |= HPT_FLAG_TRAP_CANDIDATE;
+  if (s->bethe_norm == s->bethe_norm && s->bethe_norm >= 2.0) flags |= HPT_FLAG_NORM_EXPLODED;
+  int chimax = 1;
+  for (int c : s->chi) chimax = std::max(chimax, c);
+  out->step = s->step;
+  out->t = s->step * s->cfg.dt;
+  out->C = C;
+  out->log_abs_C = logC;
+  out->sign = sign;
+  out->gate_err = s->layer_gate_err;
+  out->bethe_norm = s->bethe_norm;
+  out->max_S_over_logchi = s->layer_sfrac;
+  out->gauge_sweeps = s->gauge_sweeps;
+  out->meas_sweeps = sweeps;
+  out->gauge_delta = s->gauge_delta;
+  out->meas_delta = delta;
+  out->chi_live_max = chimax;
+  out->flags = flags;
+  return 0;
+}
+
+template <typename T>
+int layer_t(hpt_sim* s) {
+  s->layer_gate_err = 0.0;
+  s->layer_flags = 0;
+  RC(apply_field_t<T>(s));
+  for (int c = 0; c < 4; ++c) RC(gate_colour<T>(s, s->colour_bonds[c]));
+  RC(apply_field_t<T>(s));
+  s->gauge_sweeps = 0;
+  s->gauge_delta = 0.0;
+  if (s->cfg.gauge_bp) {
+    RC(gauge_bp_t<T>(s, s->cfg.bp_init, nullptr, nullptr));
+    if (s->gauge_delta >= s->cfg.bp_tol) s->layer_flags |= HPT_FLAG_BP_NOT_CONVERGED_GAUGE;
+    if (s->gauge_sweeps >= s->cfg.trap_sweeps && s->gauge_delta < s->cfg.bp_tol) s->layer_flags |= HPT_FLAG_TRAP_CANDIDATE;
+  }
+  double sf = 0.0;
+  if (s->chi_max > 1)
+    for (int b = 0; b < s->nb; ++b) {
+      double S = 0.0;
+      for (double l : s->lam[b]) {
+        const double l2 = l * l;
+        if (l2 > 0) S -= l2 * std::log(l2);
+      }
+      sf = std::max(sf, S / std::log((double)s->chi_max));
+    }
+  s->layer_sfrac = sf;
+  s->step++;
+  return 0;
+}
+
+// gate factors of exp(-i phi XX), phi = -J dt:
+// G2 = c^2 Id(x)Id + s^2 X(x)X + (cs/2) (C(x)A + A(x)C), with X(P) = XPX,
+// C(P) = i[X, P], A(P) = {X, P}  (real maps in the Pauli basis)
+void make_gate_tables(hpt_sim* s) {
+  const double phi = -s->cfg.J * s->cfg.dt;
+  const double c = std::cos(phi), sn = std::sin(phi);
+  double Id[16] = {0}, Xm[16] = {0}, Cm[16] = {0}, Am[16] = {0};
+  auto at = [](double* M, int e, int d) -> double& { return M[e + 4 * d]; };
+  for (int a = 0; a < 4; ++a) at(Id, a, a) = 1.0;
+  at(Xm, 0, 0) = 1; at(Xm, 1, 1) = 1; at(Xm, 2, 2) = -1; at(Xm, 3, 3) = -1;
+  at(Cm, 3, 2) = -2.0;  // Y -> -2 Z
+  at(Cm, 2, 3) = 2.0;   // Z -> 2 Y
+  at(Am, 1, 0) = 2.0;   // I -> 2 X
+  at(Am, 0, 1) = 2.0;   // X -> 2 I
+  for (int i = 0; i < 16; ++i) {
+    s->gf.F[0][i] = c * c * Id[i]; s->gf.H[0][i] = Id[i];
+    s->gf.F[1][i] = sn * sn * Xm[i]; s->gf.H[1][i] = Xm[i];
+    s->gf.F[2][i] = 0.5 * c * sn * Cm[i]; s->gf.H[2][i] = Am[i];
+    s->gf.F[3][i] = 0.5 * c * sn * Am[i]; s->gf.H[3][i] = Cm[i];
+  }
+  // field half-step exp(+i h dt/2 Z): X -> cos(h dt) X + sin(h dt) Y, Y -> cos(h dt) Y - sin(h dt) X
+  const double th = s->cfg.h * s->cfg.dt;
+  s->g1[0] = std::cos(th);   // x' = g1[0] x + g1[1] y
+  s->g1[1] = -std::sin(th);
+  s->g1[2] = std::sin(th);   // y' = g1[2] x + g1[3] y
+  s->g1[3] = std::cos(th);
+}
+
+template <typename T>
+int reset_t(hpt_sim* s) {
+  for (int b = 0; b < s->nb; ++b) {
+    s->chi[b] = 1;
+    s->lam[b].assign(1, 1.0);
+  }
+  for (int v = 0; v < s->N; ++v) {
+    T* p = psi_of<T>(s, v);
+    KR(launch_fill_t<T>(p, 4, 0.0, s->stream));
+    KR(launch_fill_t<T>(p + (v == s->centre ? 3 : 0), 1, 1.0, s->stream));
+  }
+  for (int b = 0; b < s->nb; ++b)
+    for (int d = 0; d < 2; ++d) KR(launch_fill_value(gmsg_slot(s, b, d), 1, 1.0, s->stream));
+  s->step = 0;
+  s->layer_gate_err = 0.0;
+  s->layer_flags = 0;
+  s->layer_sfrac = 0.0;
+  s->gauge_sweeps = 0;
+  s->gauge_delta = 0.0;
+  s->bethe_norm = 1.0;
+  return sync_stream(s);
+}
+
+}  // namespace
+}  // namespace hpt
+
+using namespace hpt;
+
+// ---------------------------------------------------------------------------
+// C ABI
+extern "C" {
+
+int hpt_config_default(hpt_config* c) {
+  if (!c) return HPT_EINVAL;
+  std::memset(c, 0, sizeof(*c));
+  c->Lx = 3; c->Ly = 3;
+  c->J = 1.0; c->h = 1.0; c->dt = 0.05;
+  c->chi_max = 8;
+  c->cx = -1; c->cy = -1;
+  c->precision = HPT_FP64;
+  c->qr_mode = HPT_QR_ADAPTIVE;
+  c->chol_min_ratio = 2;
+  c->chol_min_cols = 16;
+  c->eps_cut = 1e-11;
+  c->eps_pinv = 1e-12;
+  c->bp_alpha = 0.5;
+  c->bp_tol = 1e-10;
+  c->bp_max_sweeps = 1000;
+  c->bp_init = HPT_BP_UNIFORM;
+  c->meas_alpha = -1.0;
+  c->meas_tol = -1.0;
+  c->meas_max_sweeps = 0;
+  c->gauge_bp = 1;
+  c->trap_sweeps = 30;
+  return HPT_OK;
+}
+
+int hpt_required_bytes(const hpt_config* cfg, uint64_t* bytes) {
+  const int r = validate(cfg);
+  if (r) return r;
+  if (!bytes) return HPT_EINVAL;
+  Carve cv;
+  make_carve(*cfg, cv);
+  *bytes = cv.total;
+  return HPT_OK;
+}
+
+int hpt_state_bytes(const hpt_config* cfg, uint64_t* bytes) {
+  const int r = validate(cfg);
+  if (r) return r;
+  if (!bytes) return HPT_EINVAL;
+  std::vector<SiteInfo> sites;
+  std::vector<BondInfo> bonds;
+  build_topology(*cfg, sites, bonds);
+  const uint64_t E = cfg->precision == HPT_FP32_MFMA ? 4 : 8;
+  uint64_t tot = 0;
+  for (auto& s : sites) tot += 4ull * (uint64_t)ipow(cfg->chi_max, s.deg) * E;
+  *bytes = tot;
+  return HPT_OK;
+}
+
+int hpt_create(const hpt_config* cfg, void* arena, uint64_t arena_bytes, void* hip_stream, hpt_sim** out) {
+  if (!out) return HPT_EINVAL;
+  *out = nullptr;
+  int r = validate(cfg);
+  if (r) return r;
+  hpt_sim* s = new (std::nothrow) hpt_sim();
+  if (!s) return HPT_ENOMEM;
+  s->cfg = *cfg;
+  s->fp32 = cfg->precision == HPT_FP32_MFMA;
+  s->elem = s->fp32 ? 4 : 8;
+  s->chi_max = cfg->chi_max;
+  build_topology(*cfg, s->sites, s->bonds);
+  s->N = (int)s->sites.size();
+  s->nb = (int)s->bonds.size();
+  const int cx = cfg->cx < 0 ? (cfg->Lx - 1) / 2 : cfg->cx, cy = cfg->cy < 0 ? (cfg->Ly - 1) / 2 : cfg->cy;
+  s->centre = cx + cfg->Lx * cy;
+  s->colour_bonds.assign(4, {});
+  for (int b = 0; b < s->nb; ++b) s->colour_bonds[s->bonds[b].colour].push_back(b);
+  s->chi.assign(s->nb, 1);
+  s->lam.assign(s->nb, std::vector<double>(1, 1.0));
+  make_carve(*cfg, s->cv);
+  s->stream = (hipStream_t)hip_stream;
+  if (arena) {
+    if (arena_bytes < s->cv.total) { delete s; return HPT_ENOMEM; }
+    if (((uintptr_t)arena) % ALIGN) { delete s; return HPT_EINVAL; }
+    s->arena = (char*)arena;
+    s->arena_bytes = arena_bytes;
+    s->own_arena = false;
+  } else {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, s->cv.total);
+    if (e != hipSuccess) { set_hip_error(e, "hipMalloc(arena)"); delete s; return e == hipErrorOutOfMemory ? HPT_ENOMEM : HPT_EHIP; }
+    s->arena = (char*)p;
+    s->arena_bytes = s->cv.total;
+    s->own_arena = true;
+  }
+  char* A = s->arena;
+  for (int v = 0; v < s->N; ++v) {
+    s->sites[v].psi = A + s->cv.psi_off[v];
+    s->sites[v].cap = 4 * ipow(s->chi_max, s->sites[v].deg);
+  }
+  s->gmsg = (double*)(A + s->cv.gmsg);
+  s->gmsg_hat = (double*)(A + s->cv.gmsg_hat);
+  s->gmsg32 = s->fp32 ? (float*)(A + s->cv.gmsg32) : nullptr;
+  s->mmsg = (double*)(A + s->cv.mmsg);
+  s->mmsg_hat = (double*)(A + s->cv.mmsg_hat);
+  for (int i = 0; i < 3; ++i) s->t[i] = A + s->cv.t[i];
+  s->part = (double*)(A + s->cv.part);
+  s->meas_scr = (double*)(A + s->cv.meas_scr);
+  s->slots.resize(s->cv.max_colour_bonds);
+  for (int q = 0; q < s->cv.max_colour_bonds; ++q)
+    slot_layout(s->chi_max, s->fp32, A + s->cv.slots + (uint64_t)q * s->cv.slot_bytes, &s->slots[q]);
+  {
+    const uint64_t n4 = 4ull * s->chi_max, sz = n4 * n4 * 8;
+    char* c = A + s->cv.chol;
+    s->G1 = (double*)c; c += sz;
+    s->R1 = (double*)c; c += sz;
+    s->Ri1 = (double*)c; c += sz;
+    s->G2 = (double*)c; c += sz;
+    s->R2 = (double*)c; c += sz;
+    s->Ri2 = (double*)c; c += sz;
+    s->Ri32 = (float*)c; c += n4 * n4 * 4;
+    c += 4 * n4 * 8;
+    s->info = (int*)c;
+  }
+  {
+    char* c = A + s->cv.small;
+    s->bethe_x = (double*)c; c += (uint64_t)(s->N + s->nb + 64) * 8;
+    s->res = (double*)c; c += 16 * 8;
+    s->delta = (double*)c; c += 2ull * s->nb * 8;
+    c = (char*)(((uintptr_t)c + 255) / 256 * 256);
+    s->cores_dev = (BondCore*)c;
+  }
+  s->jobs_dev = A + s->cv.jobs;
+  s->jobs_used = 0;
+  s->hscratch_bytes = (uint64_t)s->cv.max_colour_bonds * (sizeof(BondCore) + s->chi_max * 8 + 64) + (1 << 20);
+  hipError_t e1 = hipHostMalloc((void**)&s->jobs_host, s->cv.jobs_bytes, hipHostMallocDefault);
+  hipError_t e2 = hipHostMalloc((void**)&s->hscratch, s->hscratch_bytes, hipHostMallocDefault);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    set_hip_error(e1 != hipSuccess ? e1 : e2, "hipHostMalloc");
+    if (e1 == hipSuccess) (void)hipHostFree(s->jobs_host);
+    if (e2 == hipSuccess) (void)hipHostFree(s->hscratch);
+    if (s->own_arena) (void)hipFree(s->arena);
+    delete s;
+    return HPT_EHIP;
+  }
+  make_gate_tables(s);
+  r = s->fp32 ? reset_t<float>(s) : reset_t<double>(s);
+  if (r) {
+    hpt_destroy(s);
+    return r;
+  }
+  *out = s;
+  return HPT_OK;
+}
+
+int hpt_reset(hpt_sim* s) {
+  if (!s) return HPT_EINVAL;
+  return s->fp32 ? reset_t<float>(s) : reset_t<double>(s);
+}
+
+int hpt_step(hpt_sim* s, int32_t nsteps) {
+  if (!s || nsteps < 0) return HPT_EINVAL;
+  for (int i = 0; i < nsteps; ++i) {
+    const int r = s->fp32 ? layer_t<float>(s) : layer_t<double>(s);
+    if (r) return r;
+  }
+  return HPT_OK;
+}
+
+int hpt_apply_field(hpt_sim* s) {
+  if (!s) return HPT_EINVAL;
+  const int r = s->fp32 ? apply_field_t<float>(s) : apply_field_t<double>(s);
+  if (r) return r;
+  return sync_stream(s);
+}
+
+int hpt_apply_bond(hpt_sim* s, int32_t bond) {
+  if (!s || bond < 0 || bond >= s->nb) return HPT_EINVAL;
+  std::vector<int> one(1, bond);
+  s->layer_gate_err = 0.0;
+  return s->fp32 ? gate_colour<float>(s, one) : gate_colour<double>(s, one);
+}
+
+int hpt_gauge_bp(hpt_sim* s, int32_t init, int32_t* sweeps, double* delta) {
+  if (!s || (init != HPT_BP_UNIFORM && init != HPT_BP_WARM)) return HPT_EINVAL;
+  return s->fp32 ? gauge_bp_t<float>(s, init, sweeps, delta) : gauge_bp_t<double>(s, init, sweeps, delta);
+}
+
+int hpt_measure(hpt_sim* s, hpt_measurement* out) {
+  if (!s || !out) return HPT_EINVAL;
+  return s->fp32 ? measure_t<float>(s, out) : measure_t<double>(s, out);
+}
+
+int hpt_get_chi(hpt_sim* s, int32_t bond, int32_t* chi) {
+  if (!s || !chi || bond < 0 || bond >= s->nb) return HPT_EINVAL;
+  *chi = s->chi[bond];
+  return HPT_OK;
+}
+
+int hpt_get_bond_spectrum(hpt_sim* s, int32_t bond, double* lam, int32_t cap, int32_t* chi) {
+  if (!s || bond < 0 || bond >= s->nb) return HPT_EINVAL;
+  const int n = (int)s->lam[bond].size();
+  if (chi) *chi = n;
+  if (lam) {
+    if (cap < n) return HPT_EINVAL;
+    for (int i = 0; i < n; ++i) lam[i] = s->lam[bond][i];
+  }
+  return HPT_OK;
+}
+
+int hpt_get_site_tensor(hpt_sim* s, int32_t site, double* host, uint64_t n, int32_t* dims) {
+  if (!s || site < 0 || site >= s->N) return HPT_EINVAL;
+  int64_t d[5];
+  site_dims(s, site, d);
+  const int deg = s->sites[site].deg;
+  uint64_t tot = 1;
+  for (int l = 0; l <= deg; ++l) {
+    tot *= d[l];
+    if (dims) dims[l] = (int32_t)d[l];
+  }
+  if (!host) return HPT_OK;
+  if (n < tot) return HPT_EINVAL;
+  if (sync_stream(s)) return HPT_EHIP;
+  if (s->fp32) {
+    std::vector<float> tmp(tot);
+    HPT_HIP(hipMemcpy(tmp.data(), s->sites[site].psi, tot * 4, hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < tot; ++i) host[i] = tmp[i];
+  } else {
+    HPT_HIP(hipMemcpy(host, s->sites[site].psi, tot * 8, hipMemcpyDeviceToHost));
+  }
+  return HPT_OK;
+}
+
+int hpt_set_site_tensor(hpt_sim* s, int32_t site, const double* host, const int32_t* dims) {
+  if (!s || !host || !dims || site < 0 || site >= s->N) return HPT_EINVAL;
+  const SiteInfo& si = s->sites[site];
+  uint64_t tot = 1;
+  for (int l = 0; l < si.deg; ++l) {
+    if (dims[l] < 1 || dims[l] > s->chi_max) return HPT_EINVAL;
+    tot *= dims[l];
+  }
+  if (dims[si.deg] != 4) return HPT_EINVAL;
+  tot *= 4;
+  if (sync_stream(s)) return HPT_EHIP;
+  if (s->fp32) {
+    std::vector<float> tmp(tot);
+    for (uint64_t i = 0; i < tot; ++i) tmp[i] = (float)host[i];
+    HPT_HIP(hipMemcpy(si.psi, tmp.data(), tot * 4, hipMemcpyHostToDevice));
+  } else {
+    HPT_HIP(hipMemcpy(si.psi, host, tot * 8, hipMemcpyHostToDevice));
+  }
+  for (int l = 0; l < si.deg; ++l) {
+    const int b = si.bond[l];
+    if (s->chi[b] != dims[l]) {
+      s->chi[b] = dims[l];
+      s->lam[b].assign(dims[l], 1.0 / std::sqrt((double)dims[l]));
+    }
+  }
+  return HPT_OK;
+}
+
+int hpt_get_messages(hpt_sim* s, int32_t bond, int32_t dir, double* host, int32_t cap) {
+  if (!s || !host || bond < 0 || bond >= s->nb || dir < 0 || dir > 1) return HPT_EINVAL;
+  const int c = s->chi[bond];
+  if (cap < c * c) return HPT_EINVAL;
+  if (sync_stream(s)) return HPT_EHIP;
+  HPT_HIP(hipMemcpy(host, gmsg_slot(s, bond, dir), (uint64_t)c * c * 8, hipMemcpyDeviceToHost));
+  return HPT_OK;
+}
+
+int hpt_set_messages(hpt_sim* s, int32_t bond, int32_t dir, const double* host, int32_t chi) {
+  if (!s || !host || bond < 0 || bond >= s->nb || dir < 0 || dir > 1) return HPT_EINVAL;
+  if (chi != s->chi[bond]) return HPT_EINVAL;
+  if (sync_stream(s)) return HPT_EHIP;
+  HPT_HIP(hipMemcpy(gmsg_slot(s, bond, dir), host, (uint64_t)chi * chi * 8, hipMemcpyHostToDevice));
+  return HPT_OK;
+}
+
+int hpt_get_meas_messages(hpt_sim* s, int32_t bond, int32_t dir, double* host, int32_t cap) {
+  if (!s || !host || bond < 0 || bond >= s->nb || dir < 0 || dir > 1) return HPT_EINVAL;
+  const int c = s->chi[bond];
+  if (cap < c) return HPT_EINVAL;
+  if (sync_stream(s)) return HPT_EHIP;
+  HPT_HIP(hipMemcpy(host, mmsg_slot(s, bond, dir), (uint64_t)c * 8, hipMemcpyDeviceToHost));
+  return HPT_OK;
+}
+
+int hpt_destroy(hpt_sim* s) {
+  if (!s) return HPT_EINVAL;
+  (void)hipStreamSynchronize(s->stream);
+  if (s->jobs_host) (void)hipHostFree(s->jobs_host);
+  if (s->hscratch) (void)hipHostFree(s->hscratch);
+  if (s->own_arena && s->arena) (void)hipFree(s->arena);
+  delete s;
+  return HPT_OK;
+}
+
+const char* hpt_strerror(int code) {
+  switch (code) {
+    case HPT_OK: return "ok";
+    case HPT_EINVAL: return "invalid argument";
+    case HPT_ENOMEM: return "arena too small";
+    case HPT_EHIP: return "HIP runtime error";
+    case HPT_ENUMERIC: return "numerical failure";
+    case HPT_ESTATE: return "invalid call order";
+    default: return "unknown error";
+  }
+}
+
+const char* hpt_last_hip_error(void) { return g_hip_error.c_str(); }
+
+int hpt_permute(const void* in, void* out, int32_t ndim, const int64_t* dims, const int32_t* perm,
+                int32_t elem_size, void* hip_stream) {
+  if (!in || !out || !dims || !perm || ndim < 1 || ndim > 8 || (elem_size != 4 && elem_size != 8)) return HPT_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  // a swap of two adjacent axis groups is served by the tiled path
+  int p[8];
+  for (int k = 0; k < ndim; ++k) p[k] = perm[k];
+  // detect out = [0..a-1, a+g..a+g+h-1, a..a+g-1, rest] (swap of group g and group h)
+  for (int a = 0; a < ndim; ++a)
+    for (int g = 1; a + g < ndim; ++g)
+      for (int h = 1; a + g + h <= ndim; ++h) {
+        bool ok = true;
+        for (int k = 0; k < a && ok; ++k) ok = p[k] == k;
+        for (int k = 0; k < h && ok; ++k) ok = p[a + k] == a + g + k;
+        for (int k = 0; k < g && ok; ++k) ok = p[a + h + k] == a + k;
+        for (int k = a + g + h; k < ndim && ok; ++k) ok = p[k] == k;
+        if (!ok) continue;
+        int64_t A = 1, B = 1, Cc = 1, P = 1;
+        for (int k = 0; k < a; ++k) A *= dims[k];
+        for (int k = a; k < a + g; ++k) B *= dims[k];
+        for (int k = a + g; k < a + g + h; ++k) Cc *= dims[k];
+        for (int k = a + g + h; k < ndim; ++k) P *= dims[k];
+        const int rr = permute_swap_mid(in, out, A, B, Cc, P, elem_size, st);
+        return rr == 0 ? HPT_OK : (rr == -3 ? HPT_EHIP : HPT_EINVAL);
+      }
+  int pp[8];
+  for (int k = 0; k < ndim; ++k) pp[k] = perm[k];
+  const int rr = permute_generic(in, out, ndim, dims, pp, elem_size, st);
+  return rr == 0 ? HPT_OK : (rr == -3 ? HPT_EHIP : HPT_EINVAL);
+}
+
+}  // extern "C"

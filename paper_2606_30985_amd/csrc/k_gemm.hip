@@ -1,0 +1,210 @@
+// MFMA GEMM for the dense contractions of the gate update and of the BP
+// environment products (paper Sec. "Gate Update": absorption, reconstruction
+// and deabsorption are matrix products; Sec. "Adaptive QR Decomposition":
+// the Gram matrix cv^T cv).
+//
+// One workgroup = 4 wave64s = one 64 x 64 output tile; each wave owns a
+// 32 x 32 quadrant as 2 x 2 blocks of the 16x16x4 MFMA (f64 or f32).  A and B
+// tiles of depth 16 are staged through LDS with loads coalesced along the
+// contiguous axis of each operand.  The reduction space (batch r, k-chunks)
+// can be split across workgroups; partial tiles are then summed in float64
+// by a second, deterministic kernel.
+#include "common.h"
+
+namespace hpt {
+
+namespace {
+
+constexpr int TM = 64, TN = 64, TK = 16, PAD = 2;
+
+__device__ inline d4 mfma_op(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma_op(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef d4 type; };
+template <> struct Acc<float> { typedef f4 type; };
+
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmDesc<T> d, int tiles_m, int tiles_n,
+                                                   int splits, int64_t chunks_per_r,
+                                                   double* part) {
+  typedef typename Acc<T>::type acc_t;
+  __shared__ T As[TK][TM + PAD];
+  __shared__ T Bs[TK][TN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+
+  const int64_t tiles = (int64_t)tiles_m * tiles_n;
+  const int64_t bx = blockIdx.x;
+  const int z = (int)(bx / tiles);
+  const int64_t t = bx % tiles;
+  const int tm = (int)(t % tiles_m), tn = (int)(t / tiles_m);
+  const int split = blockIdx.y;
+
+  const int64_t total = (int64_t)d.R * chunks_per_r;
+  const int64_t per = (total + splits - 1) / splits;
+  const int64_t c_begin = (int64_t)split * per;
+  const int64_t c_end = c_begin + per < total ? c_begin + per : total;
+
+  acc_t acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
+
+  const T* Az = d.A + (int64_t)z * d.sAz;
+  const T* Bz = d.B + (int64_t)z * d.sBz;
+  const int row0 = tm * TM, col0 = tn * TN;
+
+  for (int64_t c = c_begin; c < c_end; ++c) {
+    const int64_t r = c / chunks_per_r;
+    const int k0 = (int)((c % chunks_per_r) * TK);
+    const T* Ar = Az + r * d.sAr;
+    const T* Br = Bz + r * d.sBr;
+    // stage op(A) tile (TM x TK) as As[k][i]
+    if (!d.tA) {
+      const int i = tid & 63;
+      const int gi = row0 + i;
+      for (int q = 0; q < 4; ++q) {
+        const int k = (tid >> 6) + 4 * q;
+        const int gk = k0 + k;
+        T v = 0;
+        if (gi < d.M && gk < d.K) v = Ar[gi + (int64_t)gk * d.lda];
+        As[k][i] = v;
+      }
+    } else {
+      const int k = tid & 15;
+      const int gk = k0 + k;
+      for (int q = 0; q < 4; ++q) {
+        const int i = (tid >> 4) + 16 * q;
+        const int gi = row0 + i;
+        T v = 0;
+        if (gi < d.M && gk < d.K) v = Ar[gk + (int64_t)gi * d.lda];
+        As[k][i] = v;
+      }
+    }
+    // stage op(B) tile (TK x TN) as Bs[k][j]
+    if (!d.tB) {
+      const int k = tid & 15;
+      const int gk = k0 + k;
+      for (int q = 0; q < 4; ++q) {
+        const int j = (tid >> 4) + 16 * q;
+        const int gj = col0 + j;
+        T v = 0;
+        if (gj < d.N && gk < d.K) v = Br[gk + (int64_t)gj * d.ldb];
+        Bs[k][j] = v;
+      }
+    } else {
+      const int j = tid & 63;
+      const int gj = col0 + j;
+      for (int q = 0; q < 4; ++q) {
+        const int k = (tid >> 6) + 4 * q;
+        const int gk = k0 + k;
+        T v = 0;
+        if (gj < d.N && gk < d.K) v = Br[gj + (int64_t)gk * d.ldb];
+        Bs[k][j] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      T a0 = As[kr][wr * 32 + (lane & 15)];
+      T a1 = As[kr][wr * 32 + 16 + (lane & 15)];
+      T b0 = Bs[kr][wc * 32 + (lane & 15)];
+      T b1 = Bs[kr][wc * 32 + 16 + (lane & 15)];
+      acc[0][0] = mfma_op(a0, b0, acc[0][0]);
+      acc[0][1] = mfma_op(a0, b1, acc[0][1]);
+      acc[1][0] = mfma_op(a1, b0, acc[1][0]);
+      acc[1][1] = mfma_op(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+
+  // write out: block (bi, bj), register e -> row 4*(lane/16)+e, col lane%16
+  for (int bi = 0; bi < 2; ++bi)
+    for (int bj = 0; bj < 2; ++bj)
+      for (int e = 0; e < 4; ++e) {
+        const int gi = row0 + wr * 32 + bi * 16 + 4 * (lane >> 4) + e;
+        const int gj = col0 + wc * 32 + bj * 16 + (lane & 15);
+        if (gi >= d.M || gj >= d.N) continue;
+        const double v = (double)acc[bi][bj][e];
+        if (splits > 1) {
+          part[(((int64_t)split * d.Z + z) * d.N + gj) * d.M + gi] = v;
+        } else {
+          const int64_t off = (int64_t)z * d.sCz + gi + (int64_t)gj * d.ldc;
+          if (d.c_double) {
+            double* C = (double*)d.C;
+            C[off] = d.alpha * v + (d.beta != 0.0 ? d.beta * C[off] : 0.0);
+          } else {
+            T* C = (T*)d.C;
+            C[off] = (T)(d.alpha * v + (d.beta != 0.0 ? d.beta * (double)C[off] : 0.0));
+          }
+        }
+      }
+}
+
+template <typename T>
+__global__ void gemm_reduce_kernel(GemmDesc<T> d, int splits, const double* part) {
+  const int64_t mn = (int64_t)d.M * d.N;
+  const int64_t total = mn * d.Z;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int z = (int)(idx / mn);
+    const int64_t e = idx % mn;
+    const int gi = (int)(e % d.M), gj = (int)(e / d.M);
+    double s = 0.0;
+    for (int k = 0; k < splits; ++k) s += part[(((int64_t)k * d.Z + z) * d.N + gj) * d.M + gi];
+    const int64_t off = (int64_t)z * d.sCz + gi + (int64_t)gj * d.ldc;
+    if (d.c_double) {
+      double* C = (double*)d.C;
+      C[off] = d.alpha * s + (d.beta != 0.0 ? d.beta * C[off] : 0.0);
+    } else {
+      T* C = (T*)d.C;
+      C[off] = (T)(d.alpha * s + (d.beta != 0.0 ? d.beta * (double)C[off] : 0.0));
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
+  if (d.M <= 0 || d.N <= 0 || d.Z <= 0) return 0;
+  if (d.K <= 0 || d.R <= 0) return -1;  // callers never ask for an empty reduction
+  const int tiles_m = (int)ceil_div(d.M, TM), tiles_n = (int)ceil_div(d.N, TN);
+  const int64_t tiles = (int64_t)tiles_m * tiles_n * d.Z;
+  const int64_t chunks_per_r = ceil_div(d.K, TK);
+  const int64_t total = chunks_per_r * d.R;
+  // split the reduction until the grid covers the chip several times over,
+  // keeping at least 8 chunks of depth 16 per workgroup
+  int splits = 1;
+  const int64_t want = 2048;
+  while (tiles * splits < want && total / (splits * 2) >= 8) splits *= 2;
+  const int64_t need = (int64_t)splits * d.Z * d.M * d.N;
+  while (splits > 1 && need > part_cap) {
+    splits /= 2;
+  }
+  if (splits > 1 && (int64_t)splits * d.Z * d.M * d.N > part_cap) splits = 1;
+  dim3 grid((unsigned)tiles, (unsigned)splits);
+  hipLaunchKernelGGL(gemm_kernel<T>, grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
+                     chunks_per_r, part);
+  HPT_LAUNCH_CHECK("gemm_kernel");
+  if (splits > 1) {
+    const int64_t n = (int64_t)d.M * d.N * d.Z;
+    const int blocks = (int)(ceil_div(n, 256) < 65536 ? ceil_div(n, 256) : 65536);
+    hipLaunchKernelGGL(gemm_reduce_kernel<T>, dim3(blocks), dim3(256), 0, s, d, splits, part);
+    HPT_LAUNCH_CHECK("gemm_reduce_kernel");
+  }
+  return 0;
+}
+
+template int gemm<double>(const GemmDesc<double>&, double*, int64_t, hipStream_t);
+template int gemm<float>(const GemmDesc<float>&, double*, int64_t, hipStream_t);
+
+}  // namespace hpt

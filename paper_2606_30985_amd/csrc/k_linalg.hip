@@ -1,0 +1,478 @@
+// Small dense float64 factorisations of the gate update, one workgroup per
+// problem (batched over the bonds of one colour and their environment legs).
+//
+//  * pseudo_sqrt: cyclic two-sided Jacobi eigensolver (round-robin parallel
+//    ordering) and sqrt(M), M^{-1/2} with the eigenvalue cutoff
+//    (paper Algorithm "Gate update", first step; Sec. "Gate Update" item 1).
+//  * Householder QR with explicit Q (Sec. "Adaptive QR Decomposition",
+//    Householder path) -- LAPACK dlarfg/dorg2r conventions, R diagonal >= 0.
+//  * One-sided (Hestenes) Jacobi SVD (Sec. "Adaptive QR Decomposition",
+//    paragraph "SVD and Truncation").
+//  * Upper Cholesky and triangular inverse (Eq. cholqr, run as CholeskyQR2).
+//  * A plain batched float64 GEMM for the few-hundred-wide R-core products.
+#include "linalg.h"
+
+namespace hpt {
+
+namespace {
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// deterministic block sum: wave butterflies, then every thread adds the
+// per-wave partials in the same order
+__device__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < nw; ++i) r += sh[i];
+  return r;
+}
+
+// round-robin pairing: round r of n2 - 1, pair k of n2 / 2 (circle method)
+__device__ inline void rr_pair(int r, int k, int n2, int& p, int& q) {
+  const int m = n2 - 1;
+  if (k == 0) {
+    p = r;
+    q = m;
+  } else {
+    p = (r + k) % m;
+    q = (r - k + m) % m;
+  }
+}
+
+__device__ inline void jacobi_rotation(double app, double aqq, double apq, double& c, double& s) {
+  const double theta = (aqq - app) / (2.0 * apq);
+  double t;
+  if (fabs(theta) > 1e150)
+    t = 0.5 / theta;
+  else
+    t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+  c = 1.0 / sqrt(t * t + 1.0);
+  s = t * c;
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void pseudo_sqrt_kernel(const PsqJob* jobs, double eps_pinv) {
+  const PsqJob job = jobs[blockIdx.x];
+  const int n = job.n;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* A = job.work;
+  double* V = job.work + (int64_t)n * n;
+  __shared__ double cs_c[256], cs_s[256];
+  __shared__ int s_rot;
+  __shared__ double sh[16];
+  __shared__ double s_w[512];
+
+  for (int idx = tid; idx < n * n; idx += nt) {
+    const int i = idx % n, j = idx / n;
+    A[idx] = 0.5 * (job.M[i + j * n] + job.M[j + i * n]);
+    V[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int n2 = n + (n & 1);
+  const int npairs = n2 / 2;
+  if (n > 1) {
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      if (tid == 0) s_rot = 0;
+      __syncthreads();
+      for (int r = 0; r < n2 - 1; ++r) {
+        for (int k = tid; k < npairs; k += nt) {
+          int p, q;
+          rr_pair(r, k, n2, p, q);
+          double c = 1.0, s = 0.0;
+          if (p < n && q < n) {
+            const double app = A[p + p * n], aqq = A[q + q * n], apq = A[p + q * n];
+            if (apq != 0.0 && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
+              jacobi_rotation(app, aqq, apq, c, s);
+              s_rot = 1;
+            }
+          }
+          cs_c[k] = c;
+          cs_s[k] = s;
+        }
+        __syncthreads();
+        // rows p, q  (A <- J^T A)
+        for (int idx = tid; idx < npairs * n; idx += nt) {
+          const int k = idx / n, j = idx % n;
+          const double s = cs_s[k];
+          if (s == 0.0) continue;
+          int p, q;
+          rr_pair(r, k, n2, p, q);
+          const double c = cs_c[k];
+          const double ap = A[p + j * n], aq = A[q + j * n];
+          A[p + j * n] = c * ap - s * aq;
+          A[q + j * n] = s * ap + c * aq;
+        }
+        __syncthreads();
+        // columns p, q  (A <- A J, V <- V J)
+        for (int idx = tid; idx < npairs * n; idx += nt) {
+          const int k = idx / n, i = idx % n;
+          const double s = cs_s[k];
+          if (s == 0.0) continue;
+          int p, q;
+          rr_pair(r, k, n2, p, q);
+          const double c = cs_c[k];
+          const double ap = A[i + p * n], aq = A[i + q * n];
+          A[i + p * n] = c * ap - s * aq;
+          A[i + q * n] = s * ap + c * aq;
+          const double vp = V[i + p * n], vq = V[i + q * n];
+          V[i + p * n] = c * vp - s * vq;
+          V[i + q * n] = s * vp + c * vq;
+        }
+        __syncthreads();
+      }
+      if (!s_rot) break;
+      __syncthreads();
+    }
+  }
+  // eigenvalues, cutoff
+  for (int i = tid; i < n; i += nt) s_w[i] = A[i + i * n];
+  __syncthreads();
+  double wmax = -1e308;
+  for (int i = 0; i < n; ++i) wmax = fmax(wmax, s_w[i]);
+  __syncthreads();
+  if (!(wmax > 0.0)) {
+    if (tid == 0) *job.ncut = -1;
+    return;
+  }
+  if (tid == 0) {
+    int cut = 0;
+    for (int i = 0; i < n; ++i)
+      if (!(s_w[i] > eps_pinv * wmax)) ++cut;
+    *job.ncut = cut;
+  }
+  __syncthreads();
+  // S = V f(w) V^T
+  for (int idx = tid; idx < n * n; idx += nt) {
+    const int i = idx % n, j = idx / n;
+    double sq = 0.0, isq = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double w = s_w[k];
+      if (!(w > eps_pinv * wmax)) continue;
+      const double vv = V[i + k * n] * V[j + k * n];
+      const double r = sqrt(w);
+      sq += vv * r;
+      isq += vv / r;
+    }
+    job.S[idx] = sq;
+    job.Sinv[idx] = isq;
+    if (job.S32) job.S32[idx] = (float)sq;
+    if (job.Sinv32) job.Sinv32[idx] = (float)isq;
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void householder_kernel(const QrJob<T>* jobs) {
+  const QrJob<T> job = jobs[blockIdx.x];
+  if (job.gate && *job.gate == 0) return;
+  const int m = job.m, n = job.n, k = m < n ? m : n;
+  T* A = job.A;
+  const int64_t lda = job.lda;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  __shared__ double sh[16];
+  __shared__ double s_beta[1024];   // min(m, n) <= 1024 enforced by the caller
+  double* tau = job.tau;
+
+  for (int j = 0; j < k; ++j) {
+    // alpha is read before the barriers inside block_sum; thread 0 overwrites
+    // A[j, j] only after them
+    const double alpha = (double)A[j + j * lda];
+    double part = 0.0;
+    for (int i = j + 1 + tid; i < m; i += blockDim.x) {
+      const double x = (double)A[i + j * lda];
+      part += x * x;
+    }
+    const double ss = block_sum(part, sh);
+    double beta, t;
+    if (ss == 0.0) {
+      t = 0.0;
+      beta = alpha;
+    } else {
+      const double sigma = sqrt(alpha * alpha + ss);
+      beta = alpha >= 0.0 ? -sigma : sigma;
+      t = (beta - alpha) / beta;
+      const double scal = 1.0 / (alpha - beta);
+      for (int i = j + 1 + tid; i < m; i += blockDim.x)
+        A[i + j * lda] = (T)((double)A[i + j * lda] * scal);
+    }
+    if (tid == 0) {
+      tau[j] = t;
+      s_beta[j] = beta;
+      A[j + j * lda] = (T)beta;
+    }
+    __syncthreads();
+    if (t != 0.0) {
+      for (int c = j + 1 + wave; c < n; c += nw) {
+        double w = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) w += (double)A[i + j * lda] * (double)A[i + c * lda];
+        w = wave_sum(w) + (double)A[j + c * lda];
+        w *= t;
+        if (lane == 0) A[j + c * lda] = (T)((double)A[j + c * lda] - w);
+        for (int i = j + 1 + lane; i < m; i += 64)
+          A[i + c * lda] = (T)((double)A[i + c * lda] - (double)A[i + j * lda] * w);
+      }
+    }
+    __syncthreads();
+  }
+  // R with non-negative diagonal
+  for (int idx = tid; idx < k * n; idx += blockDim.x) {
+    const int i = idx % k, c = idx / k;
+    const double sg = s_beta[i] < 0.0 ? -1.0 : 1.0;
+    double v = 0.0;
+    if (c == i)
+      v = s_beta[i] * sg;
+    else if (c > i)
+      v = (double)A[i + c * lda] * sg;
+    job.R[i + (int64_t)c * job.ldr] = v;
+  }
+  __syncthreads();
+  if (!job.form_q) return;
+  for (int j = k - 1; j >= 0; --j) {
+    const double t = tau[j];
+    for (int c = j + 1 + wave; c < k; c += nw) {
+      double w = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) w += (double)A[i + j * lda] * (double)A[i + c * lda];
+      w = wave_sum(w) * t;
+      if (lane == 0) A[j + c * lda] = (T)(-w);
+      for (int i = j + 1 + lane; i < m; i += 64)
+        A[i + c * lda] = (T)((double)A[i + c * lda] - (double)A[i + j * lda] * w);
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += blockDim.x) {
+      double v;
+      if (i < j)
+        v = 0.0;
+      else if (i == j)
+        v = 1.0 - t;
+      else
+        v = -t * (double)A[i + j * lda];
+      A[i + j * lda] = (T)v;
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < m * k; idx += blockDim.x) {
+    const int i = idx % m, c = idx / m;
+    if (s_beta[c] < 0.0) A[i + c * lda] = (T)(-(double)A[i + c * lda]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdJob* jobs) {
+  const SvdJob job = jobs[blockIdx.x];
+  const int m = job.m, n = job.n;
+  double* G = job.G;
+  double* V = job.V;
+  const int ldg = job.ldg, ldv = job.ldv;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  __shared__ int s_rot;
+  __shared__ double s_sig[1024];
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int i = idx % n, j = idx / n;
+    V[i + j * ldv] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int n2 = n + (n & 1), npairs = n2 / 2;
+  const double tol = 1e-15 * sqrt((double)m);
+  int sweep = 0;
+  if (n > 1) {
+    for (sweep = 0; sweep < 60; ++sweep) {
+      if (tid == 0) s_rot = 0;
+      __syncthreads();
+      for (int r = 0; r < n2 - 1; ++r) {
+        for (int k = wave; k < npairs; k += nw) {
+          int p, q;
+          rr_pair(r, k, n2, p, q);
+          if (p >= n || q >= n) continue;
+          double a = 0.0, b = 0.0, g = 0.0;
+          for (int i = lane; i < m; i += 64) {
+            const double x = G[i + p * ldg], y = G[i + q * ldg];
+            a += x * x;
+            b += y * y;
+            g += x * y;
+          }
+          a = wave_sum(a);
+          b = wave_sum(b);
+          g = wave_sum(g);
+          if (g == 0.0 || !(fabs(g) > tol * sqrt(a * b))) continue;
+          double c, s;
+          jacobi_rotation(a, b, g, c, s);
+          for (int i = lane; i < m; i += 64) {
+            const double x = G[i + p * ldg], y = G[i + q * ldg];
+            G[i + p * ldg] = c * x - s * y;
+            G[i + q * ldg] = s * x + c * y;
+          }
+          for (int i = lane; i < n; i += 64) {
+            const double x = V[i + p * ldv], y = V[i + q * ldv];
+            V[i + p * ldv] = c * x - s * y;
+            V[i + q * ldv] = s * x + c * y;
+          }
+          if (lane == 0) s_rot = 1;
+        }
+        __syncthreads();
+      }
+      if (!s_rot) break;
+      __syncthreads();
+    }
+  }
+  for (int p = wave; p < n; p += nw) {
+    double a = 0.0;
+    for (int i = lane; i < m; i += 64) a += G[i + p * ldg] * G[i + p * ldg];
+    a = wave_sum(a);
+    if (lane == 0) s_sig[p] = sqrt(a);
+  }
+  __syncthreads();
+  for (int p = tid; p < n; p += blockDim.x) {
+    const double sp = s_sig[p];
+    int rank = 0;
+    for (int q = 0; q < n; ++q) {
+      const double sq = s_sig[q];
+      if (sq > sp || (sq == sp && q < p)) ++rank;
+    }
+    job.perm[rank] = p;
+    job.s[rank] = sp;
+  }
+  if (tid == 0 && job.sweeps) *job.sweeps = sweep;
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void cholesky_kernel(const CholJob* jobs, double rel_tol) {
+  const CholJob job = jobs[blockIdx.x];
+  if (job.gate && *job.gate == 0) return;
+  const int n = job.n;
+  const int tid = threadIdx.x;
+  double* R = job.R;
+  const int ldr = job.ldr;
+  __shared__ double col[1024];
+  __shared__ double diag0[1024];
+  __shared__ double sh[16];
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int i = idx % n, j = idx / n;
+    const double g = job.G[i + (int64_t)j * job.ldg];
+    if (i == j) diag0[i] = g;
+    if (i <= j) R[i + (int64_t)j * ldr] = g;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int i = idx % n, j = idx / n;
+    if (i > j) R[i + (int64_t)j * ldr] = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double part = 0.0;
+    for (int k = tid; k < j; k += blockDim.x) {
+      const double x = R[k + (int64_t)j * ldr];
+      col[k] = x;
+      part += x * x;
+    }
+    const double ss = block_sum(part, sh);
+    const double d = R[j + (int64_t)j * ldr] - ss;
+    if (!(d > rel_tol * diag0[j]) || !(diag0[j] > 0.0)) {
+      if (tid == 0) *job.info = j + 1;
+      return;
+    }
+    const double rjj = sqrt(d);
+    __syncthreads();
+    if (tid == 0) R[j + (int64_t)j * ldr] = rjj;
+    for (int i = j + 1 + tid; i < n; i += blockDim.x) {
+      double s = R[j + (int64_t)i * ldr];
+      const double* Ri = R + (int64_t)i * ldr;
+      for (int k = 0; k < j; ++k) s -= col[k] * Ri[k];
+      R[j + (int64_t)i * ldr] = s / rjj;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *job.info = 0;
+}
+
+__global__ __launch_bounds__(256) void tri_inverse_kernel(const TriInvJob* jobs) {
+  const TriInvJob job = jobs[blockIdx.x];
+  if (job.gate && *job.gate == 0) return;
+  const int n = job.n;
+  const double* R = job.R;
+  double* Ri = job.Ri;
+  const int ldr = job.ldr, ldi = job.ldri;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    for (int i = c + 1; i < n; ++i) Ri[i + (int64_t)c * ldi] = 0.0;
+    Ri[c + (int64_t)c * ldi] = 1.0 / R[c + (int64_t)c * ldr];
+    for (int i = c - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int k = i + 1; k <= c; ++k) s += R[i + (int64_t)k * ldr] * Ri[k + (int64_t)c * ldi];
+      Ri[i + (int64_t)c * ldi] = -s / R[i + (int64_t)i * ldr];
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void small_gemm_kernel(const SmallGemmJob* jobs) {
+  const SmallGemmJob job = jobs[blockIdx.x];
+  if (job.gate && *job.gate == 0) return;
+  const int M = job.M_dev ? *job.M_dev : job.M;
+  const int N = job.N_dev ? *job.N_dev : job.N;
+  const int K = job.K_dev ? *job.K_dev : job.K;
+  for (int idx = threadIdx.x; idx < M * N; idx += blockDim.x) {
+    const int i = idx % M, j = idx / M;
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const double a = job.tA ? job.A[k + (int64_t)i * job.lda] : job.A[i + (int64_t)k * job.lda];
+      const double b = job.tB ? job.B[j + (int64_t)k * job.ldb] : job.B[k + (int64_t)j * job.ldb];
+      s += a * b;
+    }
+    double* c = job.C + i + (int64_t)j * job.ldc;
+    *c = job.alpha * s + (job.beta != 0.0 ? job.beta * *c : 0.0);
+  }
+}
+
+}  // namespace
+
+int launch_pseudo_sqrt(const PsqJob* jobs, int njobs, double eps_pinv, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  hipLaunchKernelGGL(pseudo_sqrt_kernel, dim3(njobs), dim3(256), 0, s, jobs, eps_pinv);
+  HPT_LAUNCH_CHECK("pseudo_sqrt_kernel");
+  return 0;
+}
+
+template <typename T>
+int launch_householder(const QrJob<T>* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  hipLaunchKernelGGL(householder_kernel<T>, dim3(njobs), dim3(256), 0, s, jobs);
+  HPT_LAUNCH_CHECK("householder_kernel");
+  return 0;
+}
+template int launch_householder<double>(const QrJob<double>*, int, hipStream_t);
+template int launch_householder<float>(const QrJob<float>*, int, hipStream_t);
+
+int launch_jacobi_svd(const SvdJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(njobs), dim3(1024), 0, s, jobs);
+  HPT_LAUNCH_CHECK("jacobi_svd_kernel");
+  return 0;
+}
+
+int launch_cholesky(const CholJob* jobs, int njobs, double rel_tol, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  hipLaunchKernelGGL(cholesky_kernel, dim3(njobs), dim3(256), 0, s, jobs, rel_tol);
+  HPT_LAUNCH_CHECK("cholesky_kernel");
+  return 0;
+}
+
+int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  hipLaunchKernelGGL(tri_inverse_kernel, dim3(njobs), dim3(256), 0, s, jobs);
+  HPT_LAUNCH_CHECK("tri_inverse_kernel");
+  return 0;
+}
+
+int launch_small_gemm(const SmallGemmJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  hipLaunchKernelGGL(small_gemm_kernel, dim3(njobs), dim3(1024), 0, s, jobs);
+  HPT_LAUNCH_CHECK("small_gemm_kernel");
+  return 0;
+}
+
+}  // namespace hpt

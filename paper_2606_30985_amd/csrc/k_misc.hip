@@ -1,0 +1,497 @@
+// Elementwise and reduction kernels: field half-step (row a1), BP message
+// normalisation and damping (Eq. bp, Eq. bp_tol, Eq. damping), measurement
+// contractions of the pinned network (Sec. "Correlation Function via Belief
+// Propagation", Eq. bethe_raw), the log-space sum with sign tracking
+// (Eq. bethe), and the projections used by the gauge-sign rule.
+#include "misc.h"
+
+namespace hpt {
+
+namespace {
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < nw; ++i) r += sh[i];
+  return r;
+}
+__device__ double block_max(double v, double* sh) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int i = 1; i < nw; ++i) r = fmax(r, sh[i]);
+  return r;
+}
+
+inline int grid_for(int64_t n) {
+  int64_t g = ceil_div(n, 256);
+  return (int)(g < 65536 ? (g > 0 ? g : 1) : 65536);
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void field_kernel(T* psi, int64_t slice, double gxx, double gxy, double gyx,
+                             double gyy) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < slice;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = (double)psi[i + slice], y = (double)psi[i + 2 * slice];
+    psi[i + slice] = (T)(gxx * x + gxy * y);
+    psi[i + 2 * slice] = (T)(gyx * x + gyy * y);
+  }
+}
+
+__global__ void d2f_kernel(const double* in, float* out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+
+__global__ void fill_identity_kernel(double* M, int n, double scale) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)n * n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    M[i] = (i % n == i / n) ? scale : 0.0;
+}
+
+template <typename T>
+__global__ void fill_kernel(T* v, int64_t n, double value) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = (T)value;
+}
+
+template <typename T>
+__global__ void scale_columns_kernel(T* A, int64_t lda, int64_t m, int ncols,
+                                     const double* colscale) {
+  const int64_t total = m * ncols;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i % m, c = i / m;
+    A[r + c * lda] = (T)((double)A[r + c * lda] * colscale[c]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gauge_norm_kernel(const GaugeNormJob* jobs, double alpha,
+                                                         double* delta) {
+  const GaugeNormJob job = jobs[blockIdx.x];
+  const int n = job.n;
+  __shared__ double sh[16];
+  double part = 0.0;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx % n, j = idx / n;
+    const double s = 0.5 * (job.Mh[i + j * n] + job.Mh[j + i * n]);
+    part += s * s;
+  }
+  const double nrm2 = block_sum(part, sh);
+  const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 1.0;
+  part = 0.0;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx % n, j = idx / n;
+    const double s = 0.5 * (job.Mh[i + j * n] + job.Mh[j + i * n]) * inv;
+    const double v = (1.0 - alpha) * job.Mo[idx] + alpha * s;
+    part += v * v;
+  }
+  const double nn2 = block_sum(part, sh);
+  const double inv2 = nn2 > 0.0 ? 1.0 / sqrt(nn2) : 1.0;
+  double dmax = 0.0;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx % n, j = idx / n;
+    const double s = 0.5 * (job.Mh[i + j * n] + job.Mh[j + i * n]) * inv;
+    const double v = ((1.0 - alpha) * job.Mo[idx] + alpha * s) * inv2;
+    dmax = fmax(dmax, fabs(v - job.Mo[idx]));
+  }
+  const double dm = block_max(dmax, sh);
+  // all reads of Mo are complete (barriers inside block_max)
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx % n, j = idx / n;
+    const double s = 0.5 * (job.Mh[i + j * n] + job.Mh[j + i * n]) * inv;
+    job.Mo[idx] = ((1.0 - alpha) * job.Mo[idx] + alpha * s) * inv2;
+  }
+  if (threadIdx.x == 0) delta[blockIdx.x] = dm;
+}
+
+__global__ __launch_bounds__(256) void dots_kernel(const DotJob* jobs) {
+  const DotJob job = jobs[blockIdx.x];
+  __shared__ double sh[16];
+  double part = 0.0;
+  for (int64_t i = threadIdx.x; i < job.n; i += blockDim.x) part += job.a[i] * job.b[i];
+  const double r = block_sum(part, sh);
+  if (threadIdx.x == 0) *job.out = r;
+}
+
+__global__ __launch_bounds__(256) void log_product_kernel(const double* x, int n_num, int n_den,
+                                                          const double* delta, int n_delta,
+                                                          double* res) {
+  __shared__ double sh[16];
+  double part = 0.0, neg = 0.0, zn = 0.0, zd = 0.0, dmax = 0.0;
+  for (int i = threadIdx.x; i < n_num + n_den; i += blockDim.x) {
+    const double v = x[i];
+    const bool num = i < n_num;
+    if (v == 0.0) {
+      if (num) zn = 1.0; else zd = 1.0;
+      continue;
+    }
+    part += (num ? 1.0 : -1.0) * log(fabs(v));
+    if (v < 0.0) neg += 1.0;
+  }
+  if (delta)
+    for (int i = threadIdx.x; i < n_delta; i += blockDim.x) dmax = fmax(dmax, delta[i]);
+  const double s = block_sum(part, sh);
+  const double ng = block_sum(neg, sh);
+  const double a = block_max(zn, sh);
+  const double b = block_max(zd, sh);
+  const double d = block_max(dmax, sh);
+  if (threadIdx.x == 0) {
+    res[0] = s;
+    res[1] = (((long long)ng) & 1) ? -1.0 : 1.0;
+    res[2] = a;
+    res[3] = b;
+    res[4] = d;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// measurement contraction stages
+constexpr int MEAS_CHUNK = 256;  // o (or i) values per workgroup
+
+__global__ void meas_kron_kernel(const MeasJob* jobs, int64_t max_len) {
+  const MeasJob job = jobs[blockIdx.y];
+  const int64_t tot = job.I + job.O;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const bool isx = idx < job.I;
+    int64_t rem = isx ? idx : idx - job.I;
+    const int nl = isx ? job.nx : job.ny;
+    double v = 1.0;
+    for (int l = 0; l < nl; ++l) {
+      const int d = isx ? job.xd[l] : job.yd[l];
+      const double* m = isx ? job.xm[l] : job.ym[l];
+      v *= m[rem % d];
+      rem /= d;
+    }
+    if (isx) job.x[idx] = v; else job.y[idx - job.I] = v;
+  }
+}
+
+// stage N: part[job][ochunk][r] = sum_{o in chunk} T[r + rows*o] y[o], rows = I*nk
+template <typename T>
+__global__ void meas_gemv_n_kernel(const MeasJob* jobs, int64_t max_rows_blocks, double* part,
+                                   int64_t part_stride_job, int64_t max_ochunks) {
+  const MeasJob job = jobs[blockIdx.z];
+  if (job.O <= 1) return;
+  const int64_t rows = job.I * job.nk;
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t oc = blockIdx.y;
+  const int64_t o0 = oc * MEAS_CHUNK;
+  if (o0 >= job.O || r >= rows) return;
+  const int64_t o1 = o0 + MEAS_CHUNK < job.O ? o0 + MEAS_CHUNK : job.O;
+  const T* Tp = (const T*)job.T;
+  double s = 0.0;
+  for (int64_t o = o0; o < o1; ++o) s += (double)Tp[r + rows * o] * job.y[o];
+  part[blockIdx.z * part_stride_job + oc * rows + r] = s;
+}
+
+__global__ void meas_gemv_n_reduce(const MeasJob* jobs, const double* part,
+                                   int64_t part_stride_job) {
+  const MeasJob job = jobs[blockIdx.y];
+  if (job.O <= 1) return;
+  const int64_t rows = job.I * job.nk;
+  const int64_t nch = ceil_div(job.O, MEAS_CHUNK);
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t c = 0; c < nch; ++c) s += part[blockIdx.y * part_stride_job + c * rows + r];
+    job.S[r] = s;
+  }
+}
+
+// stage T: part[job][a][ichunk] = sum_{i in chunk} S[i + I*a] x[i]; one wave per (a, chunk)
+template <typename T>
+__global__ __launch_bounds__(256) void meas_gemv_t_kernel(const MeasJob* jobs, double* part,
+                                                          int64_t part_stride_job,
+                                                          int64_t max_ichunks) {
+  const MeasJob job = jobs[blockIdx.z];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t a = blockIdx.y;
+  if (a >= job.nk) return;
+  const int64_t ic = blockIdx.x * 4 + wave;
+  const int64_t chunk = 64 * MEAS_CHUNK;
+  const int64_t i0 = ic * chunk;
+  const int64_t nich = ceil_div(job.I, chunk);
+  if (ic >= nich) return;
+  const int64_t i1 = i0 + chunk < job.I ? i0 + chunk : job.I;
+  double s = 0.0;
+  if (job.O > 1) {
+    for (int64_t i = i0 + lane; i < i1; i += 64) s += job.S[i + job.I * a] * job.x[i];
+  } else {
+    const T* Tp = (const T*)job.T;
+    for (int64_t i = i0 + lane; i < i1; i += 64) s += (double)Tp[i + job.I * a] * job.x[i];
+  }
+  s = wave_sum(s);
+  if (lane == 0) part[blockIdx.z * part_stride_job + a * nich + ic] = s;
+}
+
+__global__ void meas_gemv_t_reduce(const MeasJob* jobs, const double* part,
+                                   int64_t part_stride_job) {
+  const MeasJob job = jobs[blockIdx.x];
+  const int64_t chunk = 64 * MEAS_CHUNK;
+  const int64_t nich = ceil_div(job.I, chunk);
+  for (int64_t a = threadIdx.x; a < job.nk; a += blockDim.x) {
+    double s = 0.0;
+    for (int64_t c = 0; c < nich; ++c) s += part[blockIdx.x * part_stride_job + a * nich + c];
+    job.out[a] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void meas_norm_kernel(const MeasNormJob* jobs, double alpha,
+                                                        double* delta) {
+  const MeasNormJob job = jobs[blockIdx.x];
+  const int n = job.n;
+  __shared__ double sh[16];
+  double p1 = 0.0, p2 = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    p1 += job.mh[i] * job.mh[i];
+    p2 += job.mh[i] * job.mo[i];
+  }
+  const double nrm2 = block_sum(p1, sh);
+  const double ov = block_sum(p2, sh);
+  double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 1.0;
+  if (ov * inv < 0.0) inv = -inv;   // sign continuity
+  double p3 = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = (1.0 - alpha) * job.mo[i] + alpha * job.mh[i] * inv;
+    p3 += v * v;
+  }
+  const double nn2 = block_sum(p3, sh);
+  const double inv2 = nn2 > 0.0 ? 1.0 / sqrt(nn2) : 1.0;
+  double dmax = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = ((1.0 - alpha) * job.mo[i] + alpha * job.mh[i] * inv) * inv2;
+    dmax = fmax(dmax, fabs(v - job.mo[i]));
+  }
+  const double dm = block_max(dmax, sh);
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    job.mo[i] = ((1.0 - alpha) * job.mo[i] + alpha * job.mh[i] * inv) * inv2;
+  if (threadIdx.x == 0) delta[blockIdx.x] = dm;
+}
+
+// ---------------------------------------------------------------------------
+// SplitMix64 weights (Steele, Lea, Flood 2014): state_i = (i+1)*gamma and
+// the 64-bit finaliser; w_i = (z >> 11) * 2^-53 - 1/2
+__device__ inline double sign_weight(uint64_t i) {
+  uint64_t z = (i + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * 0x1.0p-53 - 0.5;
+}
+
+constexpr int SP_ROWS = 2048;
+// part[(chunk * n + c) * 4 + p] = sum_{r in chunk} A[r, c] w(r + m p)
+template <typename T>
+__global__ __launch_bounds__(256) void sign_proj_kernel(const T* A, int64_t lda, int64_t m, int n,
+                                                        double* part) {
+  const int64_t chunk = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = chunk * SP_ROWS;
+  const int64_t r1 = r0 + SP_ROWS < m ? r0 + SP_ROWS : m;
+  for (int c = blockIdx.x * 4 + wave; c < n; c += gridDim.x * 4) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t r = r0 + lane; r < r1; r += 64) {
+      const double a = (double)A[r + c * lda];
+      for (int p = 0; p < 4; ++p) s[p] += a * sign_weight((uint64_t)(r + m * p));
+    }
+    for (int p = 0; p < 4; ++p) {
+      const double v = wave_sum(s[p]);
+      if (lane == 0) part[(chunk * n + c) * 4 + p] = v;
+    }
+  }
+}
+
+__global__ void sign_proj_reduce(const double* part, int64_t nchunks, int n, double* z) {
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < 4 * n;
+       idx += gridDim.x * blockDim.x) {
+    const int c = idx % n, p = idx / n;
+    double s = 0.0;
+    for (int64_t k = 0; k < nchunks; ++k) s += part[(k * n + c) * 4 + p];
+    z[c + (int64_t)n * p] = s;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+template <typename T>
+int launch_field(T* psi, int64_t slice, double gxx, double gxy, double gyx, double gyy,
+                 hipStream_t s) {
+  if (slice <= 0) return 0;
+  hipLaunchKernelGGL(field_kernel<T>, dim3(grid_for(slice)), dim3(256), 0, s, psi, slice, gxx,
+                     gxy, gyx, gyy);
+  HPT_LAUNCH_CHECK("field_kernel");
+  return 0;
+}
+template int launch_field<double>(double*, int64_t, double, double, double, double, hipStream_t);
+template int launch_field<float>(float*, int64_t, double, double, double, double, hipStream_t);
+
+int launch_d2f(const double* in, float* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(d2f_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
+  HPT_LAUNCH_CHECK("d2f_kernel");
+  return 0;
+}
+
+int launch_fill_identity(double* M, int n, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(fill_identity_kernel, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, M, n,
+                     scale);
+  HPT_LAUNCH_CHECK("fill_identity_kernel");
+  return 0;
+}
+
+int launch_fill_value(double* v, int64_t n, double value, hipStream_t s) {
+  return launch_fill_t<double>(v, n, value, s);
+}
+
+template <typename T>
+int launch_fill_t(T* v, int64_t n, double value, hipStream_t s) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(fill_kernel<T>, dim3(grid_for(n)), dim3(256), 0, s, v, n, value);
+  HPT_LAUNCH_CHECK("fill_kernel");
+  return 0;
+}
+template int launch_fill_t<double>(double*, int64_t, double, hipStream_t);
+template int launch_fill_t<float>(float*, int64_t, double, hipStream_t);
+
+template <typename T>
+int launch_scale_columns(T* A, int64_t lda, int64_t m, int ncols, const double* colscale,
+                         hipStream_t s) {
+  if (m <= 0 || ncols <= 0) return 0;
+  hipLaunchKernelGGL(scale_columns_kernel<T>, dim3(grid_for(m * ncols)), dim3(256), 0, s, A, lda,
+                     m, ncols, colscale);
+  HPT_LAUNCH_CHECK("scale_columns_kernel");
+  return 0;
+}
+template int launch_scale_columns<double>(double*, int64_t, int64_t, int, const double*,
+                                          hipStream_t);
+template int launch_scale_columns<float>(float*, int64_t, int64_t, int, const double*,
+                                         hipStream_t);
+
+int launch_gauge_norm(const GaugeNormJob* jobs, int njobs, double alpha, double* delta,
+                      hipStream_t s) {
+  if (njobs <= 0) return 0;
+  hipLaunchKernelGGL(gauge_norm_kernel, dim3(njobs), dim3(256), 0, s, jobs, alpha, delta);
+  HPT_LAUNCH_CHECK("gauge_norm_kernel");
+  return 0;
+}
+
+int launch_dots(const DotJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  hipLaunchKernelGGL(dots_kernel, dim3(njobs), dim3(256), 0, s, jobs);
+  HPT_LAUNCH_CHECK("dots_kernel");
+  return 0;
+}
+
+int launch_log_product(const double* x, int n_num, int n_den, const double* delta, int n_delta,
+                       double* res, hipStream_t s) {
+  hipLaunchKernelGGL(log_product_kernel, dim3(1), dim3(256), 0, s, x, n_num, n_den, delta,
+                     n_delta, res);
+  HPT_LAUNCH_CHECK("log_product_kernel");
+  return 0;
+}
+
+int meas_contract(const MeasJob* jobs_dev, const MeasJob* jobs_host, int njobs, int is_double,
+                  double* part, int64_t part_cap, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  int64_t max_xy = 1, max_rows = 1, max_och = 1, max_ich = 1, max_nk = 1;
+  int64_t stride_n = 1, stride_t = 1;
+  for (int j = 0; j < njobs; ++j) {
+    const MeasJob& q = jobs_host[j];
+    max_xy = std::max(max_xy, q.I + q.O);
+    const int64_t rows = q.I * q.nk;
+    max_rows = std::max(max_rows, rows);
+    const int64_t och = ceil_div(q.O, MEAS_CHUNK);
+    max_och = std::max(max_och, och);
+    const int64_t ich = ceil_div(q.I, 64 * MEAS_CHUNK);
+    max_ich = std::max(max_ich, ich);
+    max_nk = std::max(max_nk, q.nk);
+    if (q.O > 1) stride_n = std::max(stride_n, och * rows);
+    stride_t = std::max(stride_t, ich * q.nk);
+  }
+  if (stride_n * njobs > part_cap || stride_t * njobs > part_cap) return -2;
+  if (njobs > 65535 || max_och > 65535 || max_nk > 65535) return -1;
+  {
+    dim3 grid((unsigned)std::min<int64_t>(ceil_div(max_xy, 256), 4096), (unsigned)njobs);
+    hipLaunchKernelGGL(meas_kron_kernel, grid, dim3(256), 0, s, jobs_dev, max_xy);
+    HPT_LAUNCH_CHECK("meas_kron_kernel");
+  }
+  {
+    dim3 grid((unsigned)ceil_div(max_rows, 256), (unsigned)max_och, (unsigned)njobs);
+    if (is_double)
+      hipLaunchKernelGGL(meas_gemv_n_kernel<double>, grid, dim3(256), 0, s, jobs_dev,
+                         ceil_div(max_rows, 256), part, stride_n, max_och);
+    else
+      hipLaunchKernelGGL(meas_gemv_n_kernel<float>, grid, dim3(256), 0, s, jobs_dev,
+                         ceil_div(max_rows, 256), part, stride_n, max_och);
+    HPT_LAUNCH_CHECK("meas_gemv_n_kernel");
+    dim3 g2((unsigned)std::min<int64_t>(ceil_div(max_rows, 256), 4096), (unsigned)njobs);
+    hipLaunchKernelGGL(meas_gemv_n_reduce, g2, dim3(256), 0, s, jobs_dev, part, stride_n);
+    HPT_LAUNCH_CHECK("meas_gemv_n_reduce");
+  }
+  {
+    dim3 grid((unsigned)ceil_div(max_ich, 4), (unsigned)max_nk, (unsigned)njobs);
+    if (is_double)
+      hipLaunchKernelGGL(meas_gemv_t_kernel<double>, grid, dim3(256), 0, s, jobs_dev, part,
+                         stride_t, max_ich);
+    else
+      hipLaunchKernelGGL(meas_gemv_t_kernel<float>, grid, dim3(256), 0, s, jobs_dev, part,
+                         stride_t, max_ich);
+    HPT_LAUNCH_CHECK("meas_gemv_t_kernel");
+    hipLaunchKernelGGL(meas_gemv_t_reduce, dim3(njobs), dim3(256), 0, s, jobs_dev, part,
+                       stride_t);
+    HPT_LAUNCH_CHECK("meas_gemv_t_reduce");
+  }
+  return 0;
+}
+
+int launch_meas_norm(const MeasNormJob* jobs, int njobs, double alpha, double* delta,
+                     hipStream_t s) {
+  if (njobs <= 0) return 0;
+  hipLaunchKernelGGL(meas_norm_kernel, dim3(njobs), dim3(256), 0, s, jobs, alpha, delta);
+  HPT_LAUNCH_CHECK("meas_norm_kernel");
+  return 0;
+}
+
+template <typename T>
+int launch_sign_projection(const T* A, int64_t lda, int64_t m, int n, double* z, double* part,
+                           int64_t part_cap, hipStream_t s) {
+  const int64_t nch = ceil_div(m, SP_ROWS);
+  if (nch * n * 4 > part_cap) return -2;
+  if (nch > 65535) return -1;
+  dim3 grid((unsigned)ceil_div(n, 4), (unsigned)nch);
+  hipLaunchKernelGGL(sign_proj_kernel<T>, grid, dim3(256), 0, s, A, lda, m, n, part);
+  HPT_LAUNCH_CHECK("sign_proj_kernel");
+  hipLaunchKernelGGL(sign_proj_reduce, dim3((unsigned)ceil_div(4 * n, 256)), dim3(256), 0, s,
+                     part, nch, n, z);
+  HPT_LAUNCH_CHECK("sign_proj_reduce");
+  return 0;
+}
+template int launch_sign_projection<double>(const double*, int64_t, int64_t, int, double*,
+                                            double*, int64_t, hipStream_t);
+template int launch_sign_projection<float>(const float*, int64_t, int64_t, int, double*, double*,
+                                           int64_t, hipStream_t);
+
+}  // namespace hpt

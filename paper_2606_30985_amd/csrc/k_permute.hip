@@ -1,0 +1,147 @@
+// Device tensor permutation (paper Sec. "GPU Tensor Permutation": the cut
+// leg is moved next to the Pauli leg before QR and moved back afterwards,
+// entirely on the device).
+//
+// The gate update only ever swaps two groups of axes between a fast group
+// and the Pauli axis: [A, B, C, P] -> [A, C, B, P] (A = legs before the cut,
+// B = the cut leg, C = legs after it).  When A is large every element map is
+// coalesced along A; when A == 1 the (B, C) plane is transposed through a
+// 64 x 64 LDS tile so that reads run along B and writes along C.  A generic
+// rank <= 8 kernel (one thread per output element) serves everything else.
+// All paths are plain copies: bit-exact.
+#include "common.h"
+
+namespace hpt {
+
+namespace {
+
+struct PermMeta {
+  int ndim;
+  int64_t out_dims[8];
+  int64_t in_stride_of_out[8];  // input stride of the axis that is output axis k
+};
+
+template <typename E>
+__global__ void permute_generic_kernel(const E* __restrict__ in, E* __restrict__ out,
+                                       PermMeta m, int64_t total) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = idx, off = 0;
+    for (int k = 0; k < m.ndim; ++k) {
+      const int64_t c = rem % m.out_dims[k];
+      rem /= m.out_dims[k];
+      off += c * m.in_stride_of_out[k];
+    }
+    out[idx] = in[off];
+  }
+}
+
+// out[a, c, b, p] = in[a, b, c, p], A large: one thread per output element
+template <typename E>
+__global__ void swap_mid_elem_kernel(const E* __restrict__ in, E* __restrict__ out, int64_t A,
+                                     int64_t B, int64_t C, int64_t total) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = idx % A;
+    int64_t rest = idx / A;
+    const int64_t c = rest % C;
+    rest /= C;
+    const int64_t b = rest % B;
+    const int64_t p = rest / B;
+    out[idx] = in[a + A * (b + B * (c + C * p))];
+  }
+}
+
+// out[a, c, b, p] = in[a, b, c, p] with small A: tile (b, c) planes through LDS.
+// grid.x over tiles of (B, C), grid.y over (a, p) slices.
+constexpr int TT = 64;
+template <typename E>
+__global__ __launch_bounds__(256) void swap_mid_tile_kernel(const E* __restrict__ in,
+                                                            E* __restrict__ out, int64_t A,
+                                                            int64_t B, int64_t C,
+                                                            int64_t tiles_b) {
+  __shared__ E tile[TT][TT + 1];
+  const int64_t tb = blockIdx.x % tiles_b, tc = blockIdx.x / tiles_b;
+  const int64_t slice = blockIdx.y;  // a + A * p
+  const int64_t a = slice % A, p = slice / A;
+  const int64_t b0 = tb * TT, c0 = tc * TT;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t in_base = a + A * (B * C * p);
+  const int64_t out_base = a + A * (C * B * p);
+  for (int r = ty; r < TT; r += 4) {
+    const int64_t b = b0 + tx, c = c0 + r;
+    if (b < B && c < C) tile[r][tx] = in[in_base + A * (b + B * c)];
+  }
+  __syncthreads();
+  for (int r = ty; r < TT; r += 4) {
+    const int64_t c = c0 + tx, b = b0 + r;
+    if (b < B && c < C) out[out_base + A * (c + C * b)] = tile[tx][r];
+  }
+}
+
+int grid_for(int64_t n) {
+  int64_t g = ceil_div(n, 256);
+  return (int)(g < 131072 ? (g > 0 ? g : 1) : 131072);
+}
+
+}  // namespace
+
+int permute_generic(const void* in, void* out, int ndim, const int64_t* dims, const int* perm,
+                    int elem, hipStream_t s) {
+  if (ndim < 1 || ndim > 8 || (elem != 4 && elem != 8)) return -1;
+  PermMeta m;
+  m.ndim = ndim;
+  int64_t in_stride[8];
+  int64_t total = 1;
+  bool seen[8] = {false, false, false, false, false, false, false, false};
+  for (int k = 0; k < ndim; ++k) {
+    if (dims[k] < 0) return -1;
+    in_stride[k] = total;
+    total *= dims[k];
+  }
+  for (int k = 0; k < ndim; ++k) {
+    if (perm[k] < 0 || perm[k] >= ndim || seen[perm[k]]) return -1;
+    seen[perm[k]] = true;
+    m.out_dims[k] = dims[perm[k]];
+    m.in_stride_of_out[k] = in_stride[perm[k]];
+  }
+  if (total == 0) return 0;
+  if (elem == 8)
+    hipLaunchKernelGGL(permute_generic_kernel<uint64_t>, dim3(grid_for(total)), dim3(256), 0, s,
+                       (const uint64_t*)in, (uint64_t*)out, m, total);
+  else
+    hipLaunchKernelGGL(permute_generic_kernel<uint32_t>, dim3(grid_for(total)), dim3(256), 0, s,
+                       (const uint32_t*)in, (uint32_t*)out, m, total);
+  HPT_LAUNCH_CHECK("permute_generic_kernel");
+  return 0;
+}
+
+int permute_swap_mid(const void* in, void* out, int64_t A, int64_t B, int64_t C, int64_t P,
+                     int elem, hipStream_t s) {
+  const int64_t total = A * B * C * P;
+  if (total == 0) return 0;
+  if (A >= 16 || B == 1 || C == 1) {
+    if (elem == 8)
+      hipLaunchKernelGGL(swap_mid_elem_kernel<uint64_t>, dim3(grid_for(total)), dim3(256), 0, s,
+                         (const uint64_t*)in, (uint64_t*)out, A, B, C, total);
+    else
+      hipLaunchKernelGGL(swap_mid_elem_kernel<uint32_t>, dim3(grid_for(total)), dim3(256), 0, s,
+                         (const uint32_t*)in, (uint32_t*)out, A, B, C, total);
+    HPT_LAUNCH_CHECK("swap_mid_elem_kernel");
+    return 0;
+  }
+  const int64_t tiles_b = ceil_div(B, TT), tiles_c = ceil_div(C, TT);
+  const int64_t slices = A * P;
+  if (slices > 65535) return -1;
+  dim3 grid((unsigned)(tiles_b * tiles_c), (unsigned)slices);
+  if (elem == 8)
+    hipLaunchKernelGGL(swap_mid_tile_kernel<uint64_t>, grid, dim3(256), 0, s,
+                       (const uint64_t*)in, (uint64_t*)out, A, B, C, tiles_b);
+  else
+    hipLaunchKernelGGL(swap_mid_tile_kernel<uint32_t>, grid, dim3(256), 0, s,
+                       (const uint32_t*)in, (uint32_t*)out, A, B, C, tiles_b);
+  HPT_LAUNCH_CHECK("swap_mid_tile_kernel");
+  return 0;
+}
+
+}  // namespace hpt

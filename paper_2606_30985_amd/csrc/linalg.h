@@ -1,0 +1,79 @@
+// Small dense float64 linear algebra on the device, one workgroup per
+// problem, batched through arrays of job descriptors in device memory.
+#pragma once
+#include "common.h"
+
+namespace hpt {
+
+// sqrt(M) and its pseudo-inverse for a symmetric PSD chi x chi message.
+struct PsqJob {
+  const double* M;     // input, n x n column-major, leading dim n
+  double* S;           // out: sqrt(M)
+  double* Sinv;        // out: pseudo-inverse of sqrt(M)
+  float* S32;          // optional float copies (may be null)
+  float* Sinv32;
+  double* work;        // 2 n^2 scratch
+  int n;
+  int* ncut;           // out: eigenvalues dropped
+};
+
+// Householder QR of a column-major m x n block in place (storage T,
+// arithmetic float64).  R (min(m,n) x n, diag >= 0) goes to R; if form_q the
+// explicit m x min(m,n) Q with matching signs overwrites A.  Runs only when
+// (gate == nullptr || *gate != 0).
+template <typename T>
+struct QrJob {
+  T* A; int64_t lda; int m, n;
+  double* R; int ldr;
+  double* tau;         // n scratch
+  int form_q;
+  const int* gate;
+};
+
+// One-sided Jacobi SVD of an m x n (m >= n) float64 block in place.
+// On exit column perm[i] of G holds sigma_i u_i, V (n x n) the right vectors,
+// s[i] the singular values in descending order.
+struct SvdJob {
+  double* G; int ldg; int m, n;
+  double* V; int ldv;
+  double* s; int* perm;
+  int* sweeps;
+};
+
+// Upper Cholesky G = R^T R of an n x n SPD block (G read, R written, may alias).
+// *info = 0 on success, j+1 if pivot j fails the relative test.
+struct CholJob {
+  const double* G; int ldg; int n;
+  double* R; int ldr;
+  int* info;
+  const int* gate;     // skip when *gate == 0 (null = always run)
+};
+
+// Inverse of an upper-triangular n x n matrix.
+struct TriInvJob {
+  const double* R; int ldr; int n;
+  double* Ri; int ldri;
+  const int* gate;
+};
+
+// Small batched float64 GEMM: C = alpha op(A) op(B) + beta C; sizes may be
+// read from device memory (m_ptr etc. override when non-null).
+struct SmallGemmJob {
+  int M, N, K;
+  const int* M_dev; const int* N_dev; const int* K_dev;
+  const double* A; int lda; int tA;
+  const double* B; int ldb; int tB;
+  double* C; int ldc;
+  double alpha, beta;
+  const int* gate;     // skip when *gate == 0 (null = always run)
+};
+
+int launch_pseudo_sqrt(const PsqJob* jobs, int njobs, double eps_pinv, hipStream_t s);
+template <typename T>
+int launch_householder(const QrJob<T>* jobs, int njobs, hipStream_t s);
+int launch_jacobi_svd(const SvdJob* jobs, int njobs, hipStream_t s);
+int launch_cholesky(const CholJob* jobs, int njobs, double rel_tol, hipStream_t s);
+int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s);
+int launch_small_gemm(const SmallGemmJob* jobs, int njobs, hipStream_t s);
+
+}  // namespace hpt

@@ -1,0 +1,82 @@
+// Elementwise, reduction and BP kernels of libhpt (k_misc.hip).
+#pragma once
+#include "common.h"
+
+namespace hpt {
+
+// ---- field half-step (row a1): rotate the X, Y Pauli slices of one site
+template <typename T>
+int launch_field(T* psi, int64_t slice, double gxx, double gxy, double gyx, double gyy,
+                 hipStream_t s);
+
+// ---- conversions / fills
+int launch_d2f(const double* in, float* out, int64_t n, hipStream_t s);
+int launch_fill_identity(double* M, int n, double scale, hipStream_t s);
+int launch_fill_value(double* v, int64_t n, double value, hipStream_t s);
+template <typename T>
+int launch_fill_t(T* v, int64_t n, double value, hipStream_t s);
+template <typename T>
+int launch_scale_columns(T* A, int64_t lda, int64_t m, int ncols, const double* colscale,
+                         hipStream_t s);
+
+// ---- gauge BP: normalise + damp one batch of directed matrix messages.
+// For message i: sym = (Mh + Mh^T)/2 normalised (Frobenius), Mn = normalise(
+// (1-alpha) Mo + alpha sym); delta[i] = max |Mn - Mo|; Mo <- Mn.
+struct GaugeNormJob {
+  double* Mo;          // n x n, in/out
+  const double* Mh;    // n x n
+  int n;
+};
+int launch_gauge_norm(const GaugeNormJob* jobs, int njobs, double alpha, double* delta,
+                      hipStream_t s);
+
+// <A, B>_F of two n-element vectors; writes the value
+struct DotJob {
+  const double* a;
+  const double* b;
+  int64_t n;
+  double* out;
+};
+int launch_dots(const DotJob* jobs, int njobs, hipStream_t s);
+
+// log-space product: res[0] = sum_i sgn_i log|x_i| (sgn = +1 for numerators,
+// -1 for denominators), res[1] = product of signs, res[2] = 1 if any x_i == 0
+// among numerators, res[3] = 1 if any x_i == 0 among denominators,
+// res[4] = max delta over n_delta entries of delta (if delta != null)
+int launch_log_product(const double* x, int n_num, int n_den, const double* delta, int n_delta,
+                       double* res, hipStream_t s);
+
+// ---- measurement BP (row a9): contraction of a pinned slice with vectors
+// on every leg except one.  out[a] = sum_{i,o} T[i + I*(a + nk*o)] x[i] y[o]
+// with x, y Kronecker products of the incoming messages of the legs before
+// and after the output leg.
+struct MeasJob {
+  const void* T;       // pinned slice (storage type)
+  int64_t I, nk, O;
+  int nx, ny;          // number of legs folded into x and y (each <= 3)
+  const double* xm[3]; int xd[3];   // message pointers and dims, first leg fastest
+  const double* ym[3]; int yd[3];
+  double* x;           // scratch, I
+  double* y;           // scratch, O
+  double* S;           // scratch, I * nk (used when O > 1)
+  double* out;         // nk
+};
+int meas_contract(const MeasJob* jobs_dev, const MeasJob* jobs_host, int njobs, int is_double,
+                  double* part, int64_t part_cap, hipStream_t s);
+
+// normalise, sign continuity, damp, normalise; delta[i] = max |mn - mo|
+struct MeasNormJob {
+  double* mo;
+  const double* mh;
+  int n;
+};
+int launch_meas_norm(const MeasNormJob* jobs, int njobs, double alpha, double* delta,
+                     hipStream_t s);
+
+// ---- sign weights: z[c + n*p] = sum_r A[r + lda*c] w(r + m*p) for an m x n
+// matrix, p = 0..3, with w the SplitMix64 weights of the gauge-sign rule
+template <typename T>
+int launch_sign_projection(const T* A, int64_t lda, int64_t m, int n, double* z, double* part,
+                           int64_t part_cap, hipStream_t s);
+
+}  // namespace hpt

@@ -1,0 +1,285 @@
+"""ctypes binding of libhpt (include/hpt.h).
+
+Argument marshalling only: every step of the method runs inside libhpt's
+HIP kernels.  PyTorch supplies the device arena (one uint8 tensor) and the
+stream.  Importing this module loads libhpt.so and fails loudly if it is not
+built.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhpt.so")
+
+HPT_FP64 = 0
+HPT_FP32_MFMA = 1
+HPT_QR_ADAPTIVE = 0
+HPT_QR_HOUSEHOLDER = 1
+HPT_BP_UNIFORM = 0
+HPT_BP_WARM = 1
+
+FLAGS = {
+    "BP_NOT_CONVERGED_GAUGE": 1 << 0,
+    "BP_NOT_CONVERGED_MEAS": 1 << 1,
+    "TRAP_CANDIDATE": 1 << 2,
+    "NORM_EXPLODED": 1 << 3,
+    "DEGENERATE_CUT": 1 << 4,
+    "PINV_CUT": 1 << 5,
+    "BETHE_ZERO": 1 << 6,
+    "QR_FALLBACK": 1 << 7,
+}
+
+
+class HptConfig(ctypes.Structure):
+    _fields_ = [
+        ("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32),
+        ("J", ctypes.c_double), ("h", ctypes.c_double), ("dt", ctypes.c_double),
+        ("chi_max", ctypes.c_int32), ("cx", ctypes.c_int32), ("cy", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("qr_mode", ctypes.c_int32),
+        ("chol_min_ratio", ctypes.c_int32), ("chol_min_cols", ctypes.c_int32),
+        ("eps_cut", ctypes.c_double), ("eps_pinv", ctypes.c_double),
+        ("bp_alpha", ctypes.c_double), ("bp_tol", ctypes.c_double),
+        ("bp_max_sweeps", ctypes.c_int32), ("bp_init", ctypes.c_int32),
+        ("meas_alpha", ctypes.c_double), ("meas_tol", ctypes.c_double),
+        ("meas_max_sweeps", ctypes.c_int32), ("gauge_bp", ctypes.c_int32),
+        ("trap_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class HptMeasurement(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int32), ("t", ctypes.c_double), ("C", ctypes.c_double),
+        ("log_abs_C", ctypes.c_double), ("sign", ctypes.c_int32),
+        ("gate_err", ctypes.c_double), ("bethe_norm", ctypes.c_double),
+        ("max_S_over_logchi", ctypes.c_double),
+        ("gauge_sweeps", ctypes.c_int32), ("meas_sweeps", ctypes.c_int32),
+        ("gauge_delta", ctypes.c_double), ("meas_delta", ctypes.c_double),
+        ("chi_live_max", ctypes.c_int32), ("flags", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libhpt.so is not built ({LIB_PATH}); run __graft_entry__.build() "
+                          "or python paper_2606_30985_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, u64, dbl = ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+    cfgp = ctypes.POINTER(HptConfig)
+    sig = {
+        "hpt_config_default": [cfgp],
+        "hpt_required_bytes": [cfgp, ctypes.POINTER(u64)],
+        "hpt_state_bytes": [cfgp, ctypes.POINTER(u64)],
+        "hpt_create": [cfgp, P, u64, P, ctypes.POINTER(P)],
+        "hpt_reset": [P],
+        "hpt_step": [P, i32],
+        "hpt_apply_field": [P],
+        "hpt_apply_bond": [P, i32],
+        "hpt_gauge_bp": [P, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)],
+        "hpt_measure": [P, ctypes.POINTER(HptMeasurement)],
+        "hpt_get_chi": [P, i32, ctypes.POINTER(i32)],
+        "hpt_get_bond_spectrum": [P, i32, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)],
+        "hpt_get_site_tensor": [P, i32, ctypes.POINTER(dbl), u64, ctypes.POINTER(i32)],
+        "hpt_set_site_tensor": [P, i32, ctypes.POINTER(dbl), ctypes.POINTER(i32)],
+        "hpt_get_messages": [P, i32, i32, ctypes.POINTER(dbl), i32],
+        "hpt_set_messages": [P, i32, i32, ctypes.POINTER(dbl), i32],
+        "hpt_get_meas_messages": [P, i32, i32, ctypes.POINTER(dbl), i32],
+        "hpt_destroy": [P],
+        "hpt_permute": [P, P, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), i32, P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.hpt_strerror.argtypes = [ctypes.c_int]
+    lib.hpt_strerror.restype = ctypes.c_char_p
+    lib.hpt_last_hip_error.argtypes = []
+    lib.hpt_last_hip_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+EXPORTED = ["hpt_config_default", "hpt_required_bytes", "hpt_state_bytes", "hpt_create",
+            "hpt_reset", "hpt_step", "hpt_apply_field", "hpt_apply_bond", "hpt_gauge_bp",
+            "hpt_measure", "hpt_get_chi", "hpt_get_bond_spectrum", "hpt_get_site_tensor",
+            "hpt_set_site_tensor", "hpt_get_messages", "hpt_set_messages",
+            "hpt_get_meas_messages", "hpt_destroy", "hpt_strerror", "hpt_last_hip_error",
+            "hpt_permute"]
+
+
+class HptError(RuntimeError):
+    def __init__(self, code, where):
+        msg = lib.hpt_strerror(code).decode()
+        hip = lib.hpt_last_hip_error().decode()
+        super().__init__(f"{where}: {msg} ({code})" + (f" [{hip}]" if code == -3 and hip else ""))
+        self.code = code
+
+
+def check(code, where):
+    if code != 0:
+        raise HptError(code, where)
+
+
+def make_config(**kw):
+    cfg = HptConfig()
+    check(lib.hpt_config_default(ctypes.byref(cfg)), "hpt_config_default")
+    names = {n for n, _ in HptConfig._fields_}
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": HPT_FP64, "fp32": HPT_FP32_MFMA, "fp32_mfma": HPT_FP32_MFMA}[v]
+        if k == "qr_mode" and isinstance(v, str):
+            v = {"adaptive": HPT_QR_ADAPTIVE, "householder": HPT_QR_HOUSEHOLDER}[v]
+        if k == "bp_init" and isinstance(v, str):
+            v = {"uniform": HPT_BP_UNIFORM, "warm": HPT_BP_WARM}[v]
+        if k not in names:
+            raise KeyError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+def required_bytes(cfg):
+    n = ctypes.c_uint64()
+    check(lib.hpt_required_bytes(ctypes.byref(cfg), ctypes.byref(n)), "hpt_required_bytes")
+    return n.value
+
+
+def state_bytes(cfg):
+    n = ctypes.c_uint64()
+    check(lib.hpt_state_bytes(ctypes.byref(cfg), ctypes.byref(n)), "hpt_state_bytes")
+    return n.value
+
+
+class Simulator:
+    """One handle of libhpt on a CUDA/HIP device via PyTorch memory and stream."""
+
+    def __init__(self, cfg=None, device="cuda:0", torch_arena=True, **kw):
+        import torch
+        self.torch = torch
+        self.cfg = cfg if cfg is not None else make_config(**kw)
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.nbytes = required_bytes(self.cfg)
+        self.arena = None
+        ptr = None
+        if torch_arena:
+            self.arena = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.arena.data_ptr()
+            ptr = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(lib.hpt_create(ctypes.byref(self.cfg), ptr, self.nbytes if ptr else 0,
+                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "hpt_create")
+        self.h = h
+        Lx, Ly = self.cfg.Lx, self.cfg.Ly
+        self.n_sites = Lx * Ly
+        self.n_bonds = (Lx - 1) * Ly + Lx * (Ly - 1)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.hpt_destroy(self.h)
+            self.h = None
+            self.arena = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self):
+        check(lib.hpt_reset(self.h), "hpt_reset")
+
+    def step(self, n=1):
+        check(lib.hpt_step(self.h, n), "hpt_step")
+
+    def apply_field(self):
+        check(lib.hpt_apply_field(self.h), "hpt_apply_field")
+
+    def apply_bond(self, b):
+        check(lib.hpt_apply_bond(self.h, b), "hpt_apply_bond")
+
+    def gauge_bp(self, init=HPT_BP_UNIFORM):
+        sw, de = ctypes.c_int32(), ctypes.c_double()
+        check(lib.hpt_gauge_bp(self.h, init, ctypes.byref(sw), ctypes.byref(de)), "hpt_gauge_bp")
+        return sw.value, de.value
+
+    def measure(self):
+        m = HptMeasurement()
+        check(lib.hpt_measure(self.h, ctypes.byref(m)), "hpt_measure")
+        return m.as_dict()
+
+    def chi(self, b):
+        c = ctypes.c_int32()
+        check(lib.hpt_get_chi(self.h, b, ctypes.byref(c)), "hpt_get_chi")
+        return c.value
+
+    def spectrum(self, b):
+        n = ctypes.c_int32()
+        check(lib.hpt_get_bond_spectrum(self.h, b, None, 0, ctypes.byref(n)), "hpt_get_bond_spectrum")
+        out = np.zeros(n.value)
+        check(lib.hpt_get_bond_spectrum(self.h, b, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        n.value, ctypes.byref(n)), "hpt_get_bond_spectrum")
+        return out
+
+    def get_site(self, v):
+        """Site tensor as a numpy array with axes (present legs U,D,L,R..., Pauli)."""
+        dims = (ctypes.c_int32 * 5)()
+        check(lib.hpt_get_site_tensor(self.h, v, None, 0, dims), "hpt_get_site_tensor")
+        deg = self._deg(v)
+        shape = tuple(dims[i] for i in range(deg + 1))
+        buf = np.zeros(int(np.prod(shape)))
+        check(lib.hpt_get_site_tensor(self.h, v, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      buf.size, dims), "hpt_get_site_tensor")
+        return buf.reshape(shape, order="F")
+
+    def set_site(self, v, T):
+        T = np.asarray(T, dtype=np.float64)
+        dims = (ctypes.c_int32 * 5)(*T.shape)
+        flat = np.ascontiguousarray(T.ravel(order="F"))
+        check(lib.hpt_set_site_tensor(self.h, v, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      dims), "hpt_set_site_tensor")
+
+    def get_message(self, b, d):
+        c = self.chi(b)
+        out = np.zeros(c * c)
+        check(lib.hpt_get_messages(self.h, b, d, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   c * c), "hpt_get_messages")
+        return out.reshape((c, c), order="F")
+
+    def set_message(self, b, d, M):
+        M = np.asarray(M, dtype=np.float64)
+        flat = np.ascontiguousarray(M.ravel(order="F"))
+        check(lib.hpt_set_messages(self.h, b, d, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   M.shape[0]), "hpt_set_messages")
+
+    def get_meas_message(self, b, d):
+        c = self.chi(b)
+        out = np.zeros(c)
+        check(lib.hpt_get_meas_messages(self.h, b, d, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        c), "hpt_get_meas_messages")
+        return out
+
+    def _deg(self, v):
+        Lx, Ly = self.cfg.Lx, self.cfg.Ly
+        x, y = v % Lx, v // Lx
+        return (y > 0) + (y < Ly - 1) + (x > 0) + (x < Lx - 1)
+
+
+def permute(src, dst, perm, stream=None):
+    """Device permutation of a column-major torch tensor (dims = src.shape[::-1]
+    viewed column-major) into dst, through hpt_permute."""
+    import torch
+    dims = list(src.shape)
+    nd = len(dims)
+    d = (ctypes.c_int64 * nd)(*dims)
+    p = (ctypes.c_int32 * nd)(*perm)
+    st = stream if stream is not None else torch.cuda.current_stream(src.device).cuda_stream
+    check(lib.hpt_permute(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nd, d, p,
+                          src.element_size(), ctypes.c_void_p(st)), "hpt_permute")

@@ -1,0 +1,72 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, validates configs and evaluates its memory model without a GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def hpt():
+    from paper_2606_30985_amd import hpt as h
+    return h
+
+
+def test_every_declared_symbol_is_exported(hpt):
+    hdr = open(os.path.join(ROOT, "include", "hpt.h")).read()
+    declared = set(re.findall(r"\b(hpt_[a-z_0-9]+)\s*\(", hdr))
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(hpt.lib, name), name
+    assert declared == set(hpt.EXPORTED)
+
+
+def test_config_defaults(hpt):
+    c = hpt.make_config()
+    assert (c.Lx, c.Ly, c.chi_max) == (3, 3, 8)
+    assert c.eps_cut == 1e-11 and c.bp_alpha == 0.5 and c.bp_tol == 1e-10
+    assert c.cx == -1 and c.cy == -1 and c.trap_sweeps == 30
+
+
+@pytest.mark.parametrize("kw", [dict(Lx=1, Ly=1), dict(Lx=0, Ly=3), dict(dt=0.0), dict(chi_max=0),
+                                dict(cx=3, cy=0), dict(precision=7), dict(bp_alpha=0.0),
+                                dict(bp_tol=-1.0), dict(chi_max=300)])
+def test_invalid_configs_rejected(hpt, kw):
+    c = hpt.make_config(**kw)
+    n = ctypes.c_uint64()
+    assert hpt.lib.hpt_required_bytes(ctypes.byref(c), ctypes.byref(n)) == -1
+
+
+def _paper_state_floats(k, l, chi):
+    # paper, Sec. "Analytic Memory Model", Eq. mem_psi (in units of sizeof(float)):
+    # (4 chi^2 + 2 (k + l - 4) chi^3 + (k - 2)(l - 2) chi^4) * D
+    return (4 * chi ** 2 + 2 * (k + l - 4) * chi ** 3 + (k - 2) * (l - 2) * chi ** 4) * 4
+
+
+@pytest.mark.parametrize("k,l,chi", [(3, 3, 8), (4, 4, 60), (10, 10, 100), (11, 11, 100), (5, 7, 13)])
+def test_state_term_matches_paper_memory_model(hpt, k, l, chi):
+    for prec, size in ((0, 8), (1, 4)):
+        c = hpt.make_config(Lx=k, Ly=l, chi_max=chi, precision=prec)
+        assert hpt.state_bytes(c) == _paper_state_floats(k, l, chi) * size
+
+
+def test_required_bytes_fit_the_large_instance(hpt):
+    # 10x10 at chi 100 in the float32 form fits well inside 288 GB of HBM,
+    # and the float64 reference run fits as well
+    c32 = hpt.make_config(Lx=10, Ly=10, chi_max=100, precision=1)
+    c64 = hpt.make_config(Lx=10, Ly=10, chi_max=100, precision=0)
+    b32, b64 = hpt.required_bytes(c32), hpt.required_bytes(c64)
+    s32 = hpt.state_bytes(c32)
+    assert s32 == pytest.approx(102.9e9, rel=0.01)
+    assert b32 < 130e9
+    assert b64 < 260e9
+    assert b64 > hpt.state_bytes(c64)
+
+
+def test_strerror(hpt):
+    assert hpt.lib.hpt_strerror(-2).decode() == "arena too small"
+    assert hpt.lib.hpt_strerror(0).decode() == "ok"

@@ -1,0 +1,46 @@
+"""GPU parity of the whole hot path against the CPU oracle, through the C ABI."""
+
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hpt():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_30985_amd import hpt as h
+    return h
+
+
+def _oracle(cfg, n):
+    from oracle.network import Config
+    from oracle.run import run
+    return run(Config(**cfg), n)
+
+
+def test_C0_is_one(hpt):
+    sim = hpt.Simulator(Lx=3, Ly=3, chi_max=8)
+    m = sim.measure()
+    assert m["C"] == pytest.approx(1.0, abs=1e-14)
+    sim.close()
+
+
+def test_config0_fp64_trajectory(hpt):
+    # 3x3, J = h = 1, dt = 0.05, 20 steps, chi_max 8, uniform-init BP, damping 0.5, tol 1e-10
+    cfg = dict(Lx=3, Ly=3, J=1.0, h=1.0, dt=0.05, chi_max=8, bp_alpha=0.5, bp_tol=1e-10)
+    recs, net = _oracle(cfg, 20)
+    sim = hpt.Simulator(**cfg)
+    worst = 0.0
+    for n in range(1, 21):
+        sim.step(1)
+        m = sim.measure()
+        d = abs(m["C"] - recs[n]["C"])
+        worst = max(worst, d)
+        print(n, m["C"], recs[n]["C"], d, m["gauge_sweeps"], recs[n]["gauge_sweeps"], flush=True)
+        assert d <= 1e-10, (n, m["C"], recs[n]["C"])
+    sim.close()
