@@ -177,6 +177,15 @@ int hpt_destroy(hpt_sim* sim);
 const char* hpt_strerror(int code);
 const char* hpt_last_hip_error(void);
 
+/* Process-wide timing of the MFMA GEMM kernel (gemm_kernel): when enabled,
+ * every launch is bracketed by HIP events on its stream.  Enabling (again)
+ * clears the counters.  hpt_profile_gemm_read waits for the recorded events
+ * and fills out4 = {launches, total milliseconds, algorithmic flops
+ * (2 M N K per product), algorithmic bytes (operands read once, result
+ * written once)}.  For the roofline report of the contractions. */
+int hpt_profile_gemm(int32_t enable);
+int hpt_profile_gemm_read(double* out4);
+
 /* Permute a column-major tensor on the device (Sec. "GPU Tensor Permutation").
  * in/out: device pointers, not overlapping; ndim <= 8; dims of the input;
  * perm[k] = input axis that becomes output axis k; elem_size 4 or 8.

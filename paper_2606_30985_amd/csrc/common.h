@@ -50,6 +50,10 @@ struct GemmDesc {
 template <typename T>
 int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s);
 
+// process-wide event timing of gemm_kernel launches
+int gemm_profile(int enable);
+int gemm_profile_read(double* out4);
+
 // Tensor permutation (k_permute.hip).
 int permute_generic(const void* in, void* out, int ndim, const int64_t* dims,
                     const int* perm, int elem, hipStream_t s);

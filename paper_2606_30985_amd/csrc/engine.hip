@@ -1374,6 +1374,17 @@ const char* hpt_strerror(int code) {
 
 const char* hpt_last_hip_error(void) { return g_hip_error.c_str(); }
 
+int hpt_profile_gemm(int32_t enable) {
+  const int r = gemm_profile(enable);
+  return r == 0 ? HPT_OK : HPT_EHIP;
+}
+
+int hpt_profile_gemm_read(double* out4) {
+  if (!out4) return HPT_EINVAL;
+  const int r = gemm_profile_read(out4);
+  return r == 0 ? HPT_OK : HPT_EHIP;
+}
+
 int hpt_permute(const void* in, void* out, int32_t ndim, const int64_t* dims, const int32_t* perm,
                 int32_t elem_size, void* hip_stream) {
   if (!in || !out || !dims || !perm || ndim < 1 || ndim > 8 || (elem_size != 4 && elem_size != 8)) return HPT_EINVAL;

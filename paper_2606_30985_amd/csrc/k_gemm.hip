@@ -126,11 +126,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc<T> d, int tiles_m, i
     __syncthreads();
   }
 
-  // write out: block (bi, bj), register e -> row 4*(lane/16)+e, col lane%16
+  // write out: block (bi, bj), register e -> col lane%16 and row
+  // 4*(lane/16)+e for the f32 MFMA, lane/16 + 4*e for the f64 MFMA
   for (int bi = 0; bi < 2; ++bi)
     for (int bj = 0; bj < 2; ++bj)
       for (int e = 0; e < 4; ++e) {
-        const int gi = row0 + wr * 32 + bi * 16 + 4 * (lane >> 4) + e;
+        const int rloc = sizeof(T) == 8 ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e;
+        const int gi = row0 + wr * 32 + bi * 16 + rloc;
         const int gj = col0 + wc * 32 + bj * 16 + (lane & 15);
         if (gi >= d.M || gj >= d.N) continue;
         const double v = (double)acc[bi][bj][e];
@@ -171,7 +173,60 @@ __global__ void gemm_reduce_kernel(GemmDesc<T> d, int splits, const double* part
   }
 }
 
+// Optional timing of every gemm_kernel launch with HIP events on the launch
+// stream (process-wide), used to report the achieved MFMA rate.
+constexpr int PROF_CAP = 4096;
+struct GemmProfile {
+  int on = 0;
+  int n = 0;
+  hipEvent_t ev[2 * PROF_CAP];
+  double launches = 0, ms = 0, flops = 0, bytes = 0;
+};
+GemmProfile g_prof;
+
+int prof_drain() {
+  for (int i = 0; i < g_prof.n; ++i) {
+    float t = 0.f;
+    hipError_t e = hipEventSynchronize(g_prof.ev[2 * i + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]);
+    if (e != hipSuccess) {
+      set_hip_error(e, "gemm profile events");
+      return -3;
+    }
+    g_prof.ms += t;
+  }
+  g_prof.n = 0;
+  return 0;
+}
+
 }  // namespace
+
+int gemm_profile(int enable) {
+  if (enable && !g_prof.on) {
+    for (int i = 0; i < 2 * PROF_CAP; ++i) HPT_HIP(hipEventCreate(&g_prof.ev[i]));
+    g_prof.on = 1;
+    g_prof.n = 0;
+  } else if (!enable && g_prof.on) {
+    int r = prof_drain();
+    for (int i = 0; i < 2 * PROF_CAP; ++i) (void)hipEventDestroy(g_prof.ev[i]);
+    g_prof.on = 0;
+    if (r) return r;
+  }
+  g_prof.launches = g_prof.ms = g_prof.flops = g_prof.bytes = 0;
+  return 0;
+}
+
+int gemm_profile_read(double* out4) {
+  if (g_prof.on) {
+    int r = prof_drain();
+    if (r) return r;
+  }
+  out4[0] = g_prof.launches;
+  out4[1] = g_prof.ms;
+  out4[2] = g_prof.flops;
+  out4[3] = g_prof.bytes;
+  return 0;
+}
 
 template <typename T>
 int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
@@ -186,15 +241,30 @@ int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
   int splits = 1;
   const int64_t want = 2048;
   while (tiles * splits < want && total / (splits * 2) >= 8) splits *= 2;
-  const int64_t need = (int64_t)splits * d.Z * d.M * d.N;
-  while (splits > 1 && need > part_cap) {
-    splits /= 2;
-  }
-  if (splits > 1 && (int64_t)splits * d.Z * d.M * d.N > part_cap) splits = 1;
+  while (splits > 1 && (int64_t)splits * d.Z * d.M * d.N > part_cap) splits /= 2;
   dim3 grid((unsigned)tiles, (unsigned)splits);
+  const bool prof = g_prof.on;
+  if (prof) {
+    if (g_prof.n == PROF_CAP) {
+      const int r = prof_drain();
+      if (r) return r;
+    }
+    HPT_HIP(hipEventRecord(g_prof.ev[2 * g_prof.n], s));
+  }
   hipLaunchKernelGGL(gemm_kernel<T>, grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
                      chunks_per_r, part);
   HPT_LAUNCH_CHECK("gemm_kernel");
+  if (prof) {
+    HPT_HIP(hipEventRecord(g_prof.ev[2 * g_prof.n + 1], s));
+    g_prof.n++;
+    g_prof.launches += 1;
+    const double M = d.M, N = d.N, K = d.K, R = d.R, Z = d.Z;
+    g_prof.flops += 2.0 * M * N * K * R * Z;
+    const double za = d.sAz ? Z : 1.0, zb = d.sBz ? Z : 1.0;
+    const double ra = d.sAr ? R : 1.0, rb = d.sBr ? R : 1.0;
+    g_prof.bytes += sizeof(T) * (M * K * ra * za + K * N * rb * zb) +
+                    (d.c_double ? 8.0 : (double)sizeof(T)) * M * N * Z;
+  }
   if (splits > 1) {
     const int64_t n = (int64_t)d.M * d.N * d.Z;
     const int blocks = (int)(ceil_div(n, 256) < 65536 ? ceil_div(n, 256) : 65536);

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void pseudo_sqrt_kernel(const PsqJob* jobs, do
           double c = 1.0, s = 0.0;
           if (p < n && q < n) {
             const double app = A[p + p * n], aqq = A[q + q * n], apq = A[p + q * n];
-            if (apq != 0.0 && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
+            if (apq != 0.0 && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
               jacobi_rotation(app, aqq, apq, c, s);
               s_rot = 1;
             }
@@ -124,6 +124,15 @@ __global__ __launch_bounds__(256) void pseudo_sqrt_kernel(const PsqJob* jobs, do
           const double vp = V[i + p * n], vq = V[i + q * n];
           V[i + p * n] = c * vp - s * vq;
           V[i + q * n] = s * vp + c * vq;
+        }
+        __syncthreads();
+        // the rotation annihilates (p, q) exactly; drop the rounding residue
+        for (int k = tid; k < npairs; k += nt) {
+          if (cs_s[k] == 0.0) continue;
+          int p, q;
+          rr_pair(r, k, n2, p, q);
+          A[p + q * n] = 0.0;
+          A[q + p * n] = 0.0;
         }
         __syncthreads();
       }

@@ -92,6 +92,8 @@ def _load():
         "hpt_get_meas_messages": [P, i32, i32, ctypes.POINTER(dbl), i32],
         "hpt_destroy": [P],
         "hpt_permute": [P, P, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), i32, P],
+        "hpt_profile_gemm": [i32],
+        "hpt_profile_gemm_read": [ctypes.POINTER(dbl)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -111,7 +113,17 @@ EXPORTED = ["hpt_config_default", "hpt_required_bytes", "hpt_state_bytes", "hpt_
             "hpt_measure", "hpt_get_chi", "hpt_get_bond_spectrum", "hpt_get_site_tensor",
             "hpt_set_site_tensor", "hpt_get_messages", "hpt_set_messages",
             "hpt_get_meas_messages", "hpt_destroy", "hpt_strerror", "hpt_last_hip_error",
-            "hpt_permute"]
+            "hpt_permute", "hpt_profile_gemm", "hpt_profile_gemm_read"]
+
+
+def profile_gemm(enable=True):
+    check(lib.hpt_profile_gemm(1 if enable else 0), "hpt_profile_gemm")
+
+
+def profile_gemm_read():
+    out = (ctypes.c_double * 4)()
+    check(lib.hpt_profile_gemm_read(out), "hpt_profile_gemm_read")
+    return dict(launches=int(out[0]), ms=out[1], flops=out[2], bytes=out[3])
 
 
 class HptError(RuntimeError):
