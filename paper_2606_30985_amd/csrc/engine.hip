@@ -842,16 +842,18 @@ template <typename T>
 int meas_outgoing(hpt_sim* s, bool only_first_leg) {
   // jobs for every (site, leg), batched within the scratch and partial budgets
   std::vector<MeasJob> batch;
-  int64_t used = 0, max_stride = 1;
+  int64_t used = 0, pused = 0;
   auto flush = [&]() -> int {
     if (batch.empty()) return 0;
+    int64_t totals[4];
+    const int64_t pneed = meas_plan(batch.data(), (int)batch.size(), totals);
+    if (pneed > s->cv.part_cap) return HPT_ENOMEM;
     MeasJob* jd;
     RC(stage(s, batch.data(), (int)batch.size(), &jd));
-    const int r = meas_contract(jd, batch.data(), (int)batch.size(), s->fp32 ? 0 : 1, s->part, s->cv.part_cap, s->stream);
-    if (r == -2) return HPT_ENOMEM;
-    KR(r);
+    KR(meas_launch(jd, (int)batch.size(), totals, s->fp32 ? 0 : 1, s->part, s->stream));
     batch.clear();
     used = 0;
+    pused = 0;
     return 0;
   };
   for (int v = 0; v < s->N; ++v) {
@@ -885,22 +887,15 @@ int meas_outgoing(hpt_sim* s, bool only_first_leg) {
       const int bk = si.bond[k];
       j.out = mmsg_hat_slot(s, bk, dir_from(s, bk, v));
       const int64_t need = j.I + j.O + (j.O > 1 ? j.I * j.nk : 0);
-      // per-job stride of the partial buffer in meas_contract
-      const int64_t stride = std::max<int64_t>(j.O > 1 ? ceil_div(j.O, 256) * j.I * j.nk : 1,
-                                               ceil_div(j.I, 64 * 256) * j.nk);
-      if (need > s->cv.meas_scr_cap || stride > s->cv.part_cap) return HPT_ENOMEM;
-      const int64_t new_stride = std::max(max_stride, stride);
-      if (used + need > s->cv.meas_scr_cap || new_stride * (int64_t)(batch.size() + 1) > s->cv.part_cap ||
-          batch.size() >= 4096) {
+      const int64_t pjob = (j.O > 1 ? ceil_div(j.O, 256) * j.I * j.nk : 0) + ceil_div(j.I, 64 * 256) * j.nk;
+      if (need > s->cv.meas_scr_cap || pjob > s->cv.part_cap) return HPT_ENOMEM;
+      if (used + need > s->cv.meas_scr_cap || pused + pjob > s->cv.part_cap || batch.size() >= 4096)
         RC(flush());
-        max_stride = stride;
-      } else {
-        max_stride = new_stride;
-      }
       j.x = s->meas_scr + used;
       j.y = j.x + j.I;
       j.S = j.y + j.O;
       used += need;
+      pused += pjob;
       batch.push_back(j);
     }
   }

@@ -151,6 +151,132 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc<T> d, int tiles_m, i
       }
 }
 
+// 128 x 128 tile, 4 waves of 64 x 64 (4 x 4 MFMA blocks each), depth-16
+// chunks double-buffered in LDS with the next chunk prefetched into registers
+// while the current one feeds the MFMAs.
+constexpr int BT = 128, BPAD = 4;
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_big_kernel(GemmDesc<T> d, int tiles_m, int tiles_n,
+                                                       int splits, int64_t chunks_per_r,
+                                                       double* part) {
+  typedef typename Acc<T>::type acc_t;
+  __shared__ T As[2][TK][BT + BPAD];
+  __shared__ T Bs[2][TK][BT + BPAD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int64_t tiles = (int64_t)tiles_m * tiles_n;
+  const int64_t bx = blockIdx.x;
+  const int z = (int)(bx / tiles);
+  const int64_t t = bx % tiles;
+  const int tm = (int)(t % tiles_m), tn = (int)(t / tiles_m);
+  const int split = blockIdx.y;
+  const int64_t total = (int64_t)d.R * chunks_per_r;
+  const int64_t per = (total + splits - 1) / splits;
+  const int64_t c_begin = (int64_t)split * per;
+  const int64_t c_end = c_begin + per < total ? c_begin + per : total;
+  const T* Az = d.A + (int64_t)z * d.sAz;
+  const T* Bz = d.B + (int64_t)z * d.sBz;
+  const int row0 = tm * BT, col0 = tn * BT;
+
+  acc_t acc[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
+
+  T ra[8], rb[8];
+  auto load = [&](int64_t c) {
+    const int64_t r = c / chunks_per_r;
+    const int k0 = (int)((c % chunks_per_r) * TK);
+    const T* Ar = Az + r * d.sAr;
+    const T* Br = Bz + r * d.sBr;
+    if (!d.tA) {
+      const int i = tid & 127, gi = row0 + i;
+      for (int q = 0; q < 8; ++q) {
+        const int gk = k0 + (tid >> 7) + 2 * q;
+        ra[q] = (gi < d.M && gk < d.K) ? Ar[gi + (int64_t)gk * d.lda] : (T)0;
+      }
+    } else {
+      const int gk = k0 + (tid & 15);
+      for (int q = 0; q < 8; ++q) {
+        const int gi = row0 + (tid >> 4) + 16 * q;
+        ra[q] = (gi < d.M && gk < d.K) ? Ar[gk + (int64_t)gi * d.lda] : (T)0;
+      }
+    }
+    if (!d.tB) {
+      const int gk = k0 + (tid & 15);
+      for (int q = 0; q < 8; ++q) {
+        const int gj = col0 + (tid >> 4) + 16 * q;
+        rb[q] = (gj < d.N && gk < d.K) ? Br[gk + (int64_t)gj * d.ldb] : (T)0;
+      }
+    } else {
+      const int j = tid & 127, gj = col0 + j;
+      for (int q = 0; q < 8; ++q) {
+        const int gk = k0 + (tid >> 7) + 2 * q;
+        rb[q] = (gj < d.N && gk < d.K) ? Br[gj + (int64_t)gk * d.ldb] : (T)0;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+    if (!d.tA) {
+      for (int q = 0; q < 8; ++q) As[buf][(tid >> 7) + 2 * q][tid & 127] = ra[q];
+    } else {
+      for (int q = 0; q < 8; ++q) As[buf][tid & 15][(tid >> 4) + 16 * q] = ra[q];
+    }
+    if (!d.tB) {
+      for (int q = 0; q < 8; ++q) Bs[buf][tid & 15][(tid >> 4) + 16 * q] = rb[q];
+    } else {
+      for (int q = 0; q < 8; ++q) Bs[buf][(tid >> 7) + 2 * q][tid & 127] = rb[q];
+    }
+  };
+
+  if (c_begin < c_end) {
+    load(c_begin);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t c = c_begin; c < c_end; ++c) {
+      const bool more = c + 1 < c_end;
+      if (more) load(c + 1);
+#pragma unroll
+      for (int kk = 0; kk < TK / 4; ++kk) {
+        const int kr = kk * 4 + (lane >> 4);
+        T a[4], b[4];
+        for (int i = 0; i < 4; ++i) a[i] = As[buf][kr][wr * 64 + i * 16 + (lane & 15)];
+        for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kr][wc * 64 + j * 16 + (lane & 15)];
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) acc[i][j] = mfma_op(a[i], b[j], acc[i][j]);
+      }
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  for (int bi = 0; bi < 4; ++bi)
+    for (int bj = 0; bj < 4; ++bj)
+      for (int e = 0; e < 4; ++e) {
+        const int rloc = sizeof(T) == 8 ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e;
+        const int gi = row0 + wr * 64 + bi * 16 + rloc;
+        const int gj = col0 + wc * 64 + bj * 16 + (lane & 15);
+        if (gi >= d.M || gj >= d.N) continue;
+        const double v = (double)acc[bi][bj][e];
+        if (splits > 1) {
+          part[(((int64_t)split * d.Z + z) * d.N + gj) * d.M + gi] = v;
+        } else {
+          const int64_t off = (int64_t)z * d.sCz + gi + (int64_t)gj * d.ldc;
+          if (d.c_double) {
+            double* C = (double*)d.C;
+            C[off] = d.alpha * v + (d.beta != 0.0 ? d.beta * C[off] : 0.0);
+          } else {
+            T* C = (T*)d.C;
+            C[off] = (T)(d.alpha * v + (d.beta != 0.0 ? d.beta * (double)C[off] : 0.0));
+          }
+        }
+      }
+}
+
 template <typename T>
 __global__ void gemm_reduce_kernel(GemmDesc<T> d, int splits, const double* part) {
   const int64_t mn = (int64_t)d.M * d.N;
@@ -232,7 +358,9 @@ template <typename T>
 int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.Z <= 0) return 0;
   if (d.K <= 0 || d.R <= 0) return -1;  // callers never ask for an empty reduction
-  const int tiles_m = (int)ceil_div(d.M, TM), tiles_n = (int)ceil_div(d.N, TN);
+  const bool big = d.M >= 96 && d.N >= 96;
+  const int tile = big ? BT : TM;
+  const int tiles_m = (int)ceil_div(d.M, tile), tiles_n = (int)ceil_div(d.N, tile);
   const int64_t tiles = (int64_t)tiles_m * tiles_n * d.Z;
   const int64_t chunks_per_r = ceil_div(d.K, TK);
   const int64_t total = chunks_per_r * d.R;
@@ -251,8 +379,12 @@ int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
     }
     HPT_HIP(hipEventRecord(g_prof.ev[2 * g_prof.n], s));
   }
-  hipLaunchKernelGGL(gemm_kernel<T>, grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
-                     chunks_per_r, part);
+  if (big)
+    hipLaunchKernelGGL(gemm_big_kernel<T>, grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
+                       chunks_per_r, part);
+  else
+    hipLaunchKernelGGL(gemm_kernel<T>, grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
+                       chunks_per_r, part);
   HPT_LAUNCH_CHECK("gemm_kernel");
   if (prof) {
     HPT_HIP(hipEventRecord(g_prof.ev[2 * g_prof.n + 1], s));

@@ -351,16 +351,18 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdJob* jobs) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void cholesky_kernel(const CholJob* jobs, double rel_tol) {
+// Left-looking upper Cholesky; at step j every later column i needs the dot
+// of columns j and i above row j: one wave per column, lanes over rows.
+__global__ __launch_bounds__(1024) void cholesky_kernel(const CholJob* jobs, double rel_tol) {
   const CholJob job = jobs[blockIdx.x];
   if (job.gate && *job.gate == 0) return;
   const int n = job.n;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   double* R = job.R;
   const int ldr = job.ldr;
-  __shared__ double col[1024];
   __shared__ double diag0[1024];
   __shared__ double sh[16];
+  __shared__ int s_fail;
   for (int idx = tid; idx < n * n; idx += blockDim.x) {
     const int i = idx % n, j = idx / n;
     const double g = job.G[i + (int64_t)j * job.ldg];
@@ -372,49 +374,72 @@ __global__ __launch_bounds__(256) void cholesky_kernel(const CholJob* jobs, doub
     const int i = idx % n, j = idx / n;
     if (i > j) R[i + (int64_t)j * ldr] = 0.0;
   }
+  if (tid == 0) s_fail = 0;
   __syncthreads();
   for (int j = 0; j < n; ++j) {
-    double part = 0.0;
-    for (int k = tid; k < j; k += blockDim.x) {
-      const double x = R[k + (int64_t)j * ldr];
-      col[k] = x;
-      part += x * x;
+    const double* Rj = R + (int64_t)j * ldr;
+    // pivot: wave 0 reduces the column above the diagonal
+    if (wave == 0) {
+      double part = 0.0;
+      for (int k = lane; k < j; k += 64) part += Rj[k] * Rj[k];
+      part = wave_sum(part);
+      if (lane == 0) {
+        const double d = Rj[j] - part;
+        if (!(d > rel_tol * diag0[j]) || !(diag0[j] > 0.0)) {
+          s_fail = j + 1;
+        } else {
+          sh[0] = sqrt(d);
+          R[j + (int64_t)j * ldr] = sh[0];
+        }
+      }
     }
-    const double ss = block_sum(part, sh);
-    const double d = R[j + (int64_t)j * ldr] - ss;
-    if (!(d > rel_tol * diag0[j]) || !(diag0[j] > 0.0)) {
-      if (tid == 0) *job.info = j + 1;
+    __syncthreads();
+    if (s_fail) {
+      if (tid == 0) *job.info = s_fail;
       return;
     }
-    const double rjj = sqrt(d);
-    __syncthreads();
-    if (tid == 0) R[j + (int64_t)j * ldr] = rjj;
-    for (int i = j + 1 + tid; i < n; i += blockDim.x) {
-      double s = R[j + (int64_t)i * ldr];
+    const double rjj = sh[0];
+    for (int i = j + 1 + wave; i < n; i += nw) {
       const double* Ri = R + (int64_t)i * ldr;
-      for (int k = 0; k < j; ++k) s -= col[k] * Ri[k];
-      R[j + (int64_t)i * ldr] = s / rjj;
+      double part = 0.0;
+      for (int k = lane; k < j; k += 64) part += Rj[k] * Ri[k];
+      part = wave_sum(part);
+      if (lane == 0) R[j + (int64_t)i * ldr] = (Ri[j] - part) / rjj;
     }
     __syncthreads();
   }
   if (tid == 0) *job.info = 0;
 }
 
-__global__ __launch_bounds__(256) void tri_inverse_kernel(const TriInvJob* jobs) {
+// Inverse of an upper-triangular R: Y = (R^T)^{-1} is lower triangular and
+// column c of Y follows from forward substitution with the columns of R
+// (contiguous reads); one wave per column, lanes over the inner index.
+// Rinv = Y^T.
+__global__ __launch_bounds__(1024) void tri_inverse_kernel(const TriInvJob* jobs) {
   const TriInvJob job = jobs[blockIdx.x];
   if (job.gate && *job.gate == 0) return;
   const int n = job.n;
   const double* R = job.R;
   double* Ri = job.Ri;
   const int ldr = job.ldr, ldi = job.ldri;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    for (int i = c + 1; i < n; ++i) Ri[i + (int64_t)c * ldi] = 0.0;
-    Ri[c + (int64_t)c * ldi] = 1.0 / R[c + (int64_t)c * ldr];
-    for (int i = c - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int k = i + 1; k <= c; ++k) s += R[i + (int64_t)k * ldr] * Ri[k + (int64_t)c * ldi];
-      Ri[i + (int64_t)c * ldi] = -s / R[i + (int64_t)i * ldr];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  __shared__ double ybuf[16][1024];
+  double* y = ybuf[wave];
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int i = idx % n, c = idx / n;
+    if (i > c) Ri[i + (int64_t)c * ldi] = 0.0;
+  }
+  for (int c = wave; c < n; c += nw) {
+    // y[i] for i >= c: y[c] = 1/R[c,c]; y[i] = -(sum_{c<=k<i} R[k,i] y[k]) / R[i,i]
+    if (lane == 0) y[c] = 1.0 / R[c + (int64_t)c * ldr];
+    for (int i = c + 1; i < n; ++i) {
+      const double* Rc = R + (int64_t)i * ldr;
+      double part = 0.0;
+      for (int k = c + lane; k < i; k += 64) part += Rc[k] * y[k];
+      part = wave_sum(part);
+      if (lane == 0) y[i] = -part / Rc[i];
     }
+    for (int i = c + lane; i < n; i += 64) Ri[c + (int64_t)i * ldi] = y[i];
   }
 }
 
@@ -465,14 +490,14 @@ int launch_jacobi_svd(const SvdJob* jobs, int njobs, hipStream_t s) {
 
 int launch_cholesky(const CholJob* jobs, int njobs, double rel_tol, hipStream_t s) {
   if (njobs <= 0) return 0;
-  hipLaunchKernelGGL(cholesky_kernel, dim3(njobs), dim3(256), 0, s, jobs, rel_tol);
+  hipLaunchKernelGGL(cholesky_kernel, dim3(njobs), dim3(1024), 0, s, jobs, rel_tol);
   HPT_LAUNCH_CHECK("cholesky_kernel");
   return 0;
 }
 
 int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s) {
   if (njobs <= 0) return 0;
-  hipLaunchKernelGGL(tri_inverse_kernel, dim3(njobs), dim3(256), 0, s, jobs);
+  hipLaunchKernelGGL(tri_inverse_kernel, dim3(njobs), dim3(1024), 0, s, jobs);
   HPT_LAUNCH_CHECK("tri_inverse_kernel");
   return 0;
 }

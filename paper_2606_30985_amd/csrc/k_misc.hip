@@ -166,95 +166,101 @@ __global__ __launch_bounds__(256) void log_product_kernel(const double* x, int n
 }
 
 // ---------------------------------------------------------------------------
-// measurement contraction stages
-constexpr int MEAS_CHUNK = 256;  // o (or i) values per workgroup
+// measurement contraction stages; every stage launches exactly the blocks
+// the jobs need (per-job block ranges, binary search of the job)
+constexpr int MEAS_CHUNK = 256;  // o values per gemv_n block, i chunk = 64 * MEAS_CHUNK
+constexpr int MEAS_TW = 4;       // waves per gemv_t block
 
-__global__ void meas_kron_kernel(const MeasJob* jobs, int64_t max_len) {
-  const MeasJob job = jobs[blockIdx.y];
-  const int64_t tot = job.I + job.O;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const bool isx = idx < job.I;
-    int64_t rem = isx ? idx : idx - job.I;
-    const int nl = isx ? job.nx : job.ny;
-    double v = 1.0;
-    for (int l = 0; l < nl; ++l) {
-      const int d = isx ? job.xd[l] : job.yd[l];
-      const double* m = isx ? job.xm[l] : job.ym[l];
-      v *= m[rem % d];
-      rem /= d;
-    }
-    if (isx) job.x[idx] = v; else job.y[idx - job.I] = v;
+__device__ inline int find_job(const MeasJob* jobs, int njobs, int64_t b, int which) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t st = which == 0 ? jobs[mid].bk0 : which == 1 ? jobs[mid].bn0 : which == 2 ? jobs[mid].bt0 : jobs[mid].br0;
+    if (st <= b) lo = mid; else hi = mid - 1;
   }
+  return lo;
 }
 
-// stage N: part[job][ochunk][r] = sum_{o in chunk} T[r + rows*o] y[o], rows = I*nk
+__global__ void meas_kron_kernel(const MeasJob* jobs, int njobs) {
+  const int j = find_job(jobs, njobs, blockIdx.x, 0);
+  const MeasJob& job = jobs[j];
+  const int64_t idx = (blockIdx.x - job.bk0) * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= job.I + job.O) return;
+  const bool isx = idx < job.I;
+  int64_t rem = isx ? idx : idx - job.I;
+  const int nl = isx ? job.nx : job.ny;
+  double v = 1.0;
+  for (int l = 0; l < nl; ++l) {
+    const int d = isx ? job.xd[l] : job.yd[l];
+    const double* m = isx ? job.xm[l] : job.ym[l];
+    v *= m[rem % d];
+    rem /= d;
+  }
+  if (isx) job.x[idx] = v; else job.y[idx - job.I] = v;
+}
+
+// part[pn_off + oc * rows + r] = sum_{o in chunk oc} T[r + rows * o] y[o]
 template <typename T>
-__global__ void meas_gemv_n_kernel(const MeasJob* jobs, int64_t max_rows_blocks, double* part,
-                                   int64_t part_stride_job, int64_t max_ochunks) {
-  const MeasJob job = jobs[blockIdx.z];
-  if (job.O <= 1) return;
+__global__ void meas_gemv_n_kernel(const MeasJob* jobs, int njobs, double* part) {
+  const int j = find_job(jobs, njobs, blockIdx.x, 1);
+  const MeasJob& job = jobs[j];
   const int64_t rows = job.I * job.nk;
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t oc = blockIdx.y;
+  const int64_t rb = ceil_div(rows, 256);
+  const int64_t b = blockIdx.x - job.bn0;
+  const int64_t r = (b % rb) * 256 + threadIdx.x;
+  const int64_t oc = b / rb;
+  if (r >= rows) return;
   const int64_t o0 = oc * MEAS_CHUNK;
-  if (o0 >= job.O || r >= rows) return;
   const int64_t o1 = o0 + MEAS_CHUNK < job.O ? o0 + MEAS_CHUNK : job.O;
   const T* Tp = (const T*)job.T;
-  double s = 0.0;
-  for (int64_t o = o0; o < o1; ++o) s += (double)Tp[r + rows * o] * job.y[o];
-  part[blockIdx.z * part_stride_job + oc * rows + r] = s;
+  double acc = 0.0;
+  for (int64_t o = o0; o < o1; ++o) acc += (double)Tp[r + rows * o] * job.y[o];
+  part[job.pn_off + oc * rows + r] = acc;
 }
 
-__global__ void meas_gemv_n_reduce(const MeasJob* jobs, const double* part,
-                                   int64_t part_stride_job) {
-  const MeasJob job = jobs[blockIdx.y];
-  if (job.O <= 1) return;
+__global__ void meas_gemv_n_reduce(const MeasJob* jobs, int njobs, const double* part) {
+  const int j = find_job(jobs, njobs, blockIdx.x, 3);
+  const MeasJob& job = jobs[j];
   const int64_t rows = job.I * job.nk;
+  const int64_t r = (blockIdx.x - job.br0) * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= rows) return;
   const int64_t nch = ceil_div(job.O, MEAS_CHUNK);
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
-       r += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int64_t c = 0; c < nch; ++c) s += part[blockIdx.y * part_stride_job + c * rows + r];
-    job.S[r] = s;
-  }
+  double acc = 0.0;
+  for (int64_t c = 0; c < nch; ++c) acc += part[job.pn_off + c * rows + r];
+  job.S[r] = acc;
 }
 
-// stage T: part[job][a][ichunk] = sum_{i in chunk} S[i + I*a] x[i]; one wave per (a, chunk)
+// part[pt_off + a * nich + ic] = sum_{i in chunk ic} S[i + I a] x[i]; one wave per (a, ic)
 template <typename T>
-__global__ __launch_bounds__(256) void meas_gemv_t_kernel(const MeasJob* jobs, double* part,
-                                                          int64_t part_stride_job,
-                                                          int64_t max_ichunks) {
-  const MeasJob job = jobs[blockIdx.z];
+__global__ __launch_bounds__(256) void meas_gemv_t_kernel(const MeasJob* jobs, int njobs, double* part) {
+  const int j = find_job(jobs, njobs, blockIdx.x, 2);
+  const MeasJob& job = jobs[j];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t a = blockIdx.y;
-  if (a >= job.nk) return;
-  const int64_t ic = blockIdx.x * 4 + wave;
   const int64_t chunk = 64 * MEAS_CHUNK;
-  const int64_t i0 = ic * chunk;
   const int64_t nich = ceil_div(job.I, chunk);
-  if (ic >= nich) return;
+  const int64_t w = (blockIdx.x - job.bt0) * MEAS_TW + wave;
+  if (w >= nich * job.nk) return;
+  const int64_t a = w / nich, ic = w % nich;
+  const int64_t i0 = ic * chunk;
   const int64_t i1 = i0 + chunk < job.I ? i0 + chunk : job.I;
-  double s = 0.0;
+  double acc = 0.0;
   if (job.O > 1) {
-    for (int64_t i = i0 + lane; i < i1; i += 64) s += job.S[i + job.I * a] * job.x[i];
+    for (int64_t i = i0 + lane; i < i1; i += 64) acc += job.S[i + job.I * a] * job.x[i];
   } else {
     const T* Tp = (const T*)job.T;
-    for (int64_t i = i0 + lane; i < i1; i += 64) s += (double)Tp[i + job.I * a] * job.x[i];
+    for (int64_t i = i0 + lane; i < i1; i += 64) acc += (double)Tp[i + job.I * a] * job.x[i];
   }
-  s = wave_sum(s);
-  if (lane == 0) part[blockIdx.z * part_stride_job + a * nich + ic] = s;
+  acc = wave_sum(acc);
+  if (lane == 0) part[job.pt_off + a * nich + ic] = acc;
 }
 
-__global__ void meas_gemv_t_reduce(const MeasJob* jobs, const double* part,
-                                   int64_t part_stride_job) {
-  const MeasJob job = jobs[blockIdx.x];
-  const int64_t chunk = 64 * MEAS_CHUNK;
-  const int64_t nich = ceil_div(job.I, chunk);
+__global__ void meas_gemv_t_reduce(const MeasJob* jobs, const double* part) {
+  const MeasJob& job = jobs[blockIdx.x];
+  const int64_t nich = ceil_div(job.I, 64 * MEAS_CHUNK);
   for (int64_t a = threadIdx.x; a < job.nk; a += blockDim.x) {
-    double s = 0.0;
-    for (int64_t c = 0; c < nich; ++c) s += part[blockIdx.x * part_stride_job + a * nich + c];
-    job.out[a] = s;
+    double acc = 0.0;
+    for (int64_t c = 0; c < nich; ++c) acc += part[job.pt_off + a * nich + c];
+    job.out[a] = acc;
   }
 }
 
@@ -413,57 +419,65 @@ int launch_log_product(const double* x, int n_num, int n_den, const double* delt
   return 0;
 }
 
-int meas_contract(const MeasJob* jobs_dev, const MeasJob* jobs_host, int njobs, int is_double,
-                  double* part, int64_t part_cap, hipStream_t s) {
-  if (njobs <= 0) return 0;
-  int64_t max_xy = 1, max_rows = 1, max_och = 1, max_ich = 1, max_nk = 1;
-  int64_t stride_n = 1, stride_t = 1;
+int64_t meas_plan(MeasJob* jobs, int njobs, int64_t totals[4]) {
+  int64_t bk = 0, bn = 0, bt = 0, br = 0, part = 0;
   for (int j = 0; j < njobs; ++j) {
-    const MeasJob& q = jobs_host[j];
-    max_xy = std::max(max_xy, q.I + q.O);
+    MeasJob& q = jobs[j];
+    q.bk0 = bk;
+    bk += ceil_div(q.I + q.O, 256);
     const int64_t rows = q.I * q.nk;
-    max_rows = std::max(max_rows, rows);
-    const int64_t och = ceil_div(q.O, MEAS_CHUNK);
-    max_och = std::max(max_och, och);
-    const int64_t ich = ceil_div(q.I, 64 * MEAS_CHUNK);
-    max_ich = std::max(max_ich, ich);
-    max_nk = std::max(max_nk, q.nk);
-    if (q.O > 1) stride_n = std::max(stride_n, och * rows);
-    stride_t = std::max(stride_t, ich * q.nk);
+    q.bn0 = bn;
+    q.br0 = br;
+    q.pn_off = part;
+    if (q.O > 1) {
+      bn += ceil_div(rows, 256) * ceil_div(q.O, MEAS_CHUNK);
+      br += ceil_div(rows, 256);
+      part += ceil_div(q.O, MEAS_CHUNK) * rows;
+    }
+    const int64_t nich = ceil_div(q.I, 64 * MEAS_CHUNK);
+    q.bt0 = bt;
+    bt += ceil_div(nich * q.nk, MEAS_TW);
+    q.pt_off = part;
+    part += nich * q.nk;
   }
-  if (stride_n * njobs > part_cap || stride_t * njobs > part_cap) return -2;
-  if (njobs > 65535 || max_och > 65535 || max_nk > 65535) return -1;
-  {
-    dim3 grid((unsigned)std::min<int64_t>(ceil_div(max_xy, 256), 4096), (unsigned)njobs);
-    hipLaunchKernelGGL(meas_kron_kernel, grid, dim3(256), 0, s, jobs_dev, max_xy);
+  totals[0] = bk;
+  totals[1] = bn;
+  totals[2] = bt;
+  totals[3] = br;
+  return part;
+}
+
+int meas_launch(const MeasJob* jobs_dev, int njobs, const int64_t totals[4], int is_double,
+                double* part, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  for (int k = 0; k < 4; ++k)
+    if (totals[k] > 0x7fffffffll) return -1;
+  if (totals[0] > 0) {
+    hipLaunchKernelGGL(meas_kron_kernel, dim3((unsigned)totals[0]), dim3(256), 0, s, jobs_dev, njobs);
     HPT_LAUNCH_CHECK("meas_kron_kernel");
   }
-  {
-    dim3 grid((unsigned)ceil_div(max_rows, 256), (unsigned)max_och, (unsigned)njobs);
+  if (totals[1] > 0) {
     if (is_double)
-      hipLaunchKernelGGL(meas_gemv_n_kernel<double>, grid, dim3(256), 0, s, jobs_dev,
-                         ceil_div(max_rows, 256), part, stride_n, max_och);
+      hipLaunchKernelGGL(meas_gemv_n_kernel<double>, dim3((unsigned)totals[1]), dim3(256), 0, s, jobs_dev,
+                         njobs, part);
     else
-      hipLaunchKernelGGL(meas_gemv_n_kernel<float>, grid, dim3(256), 0, s, jobs_dev,
-                         ceil_div(max_rows, 256), part, stride_n, max_och);
+      hipLaunchKernelGGL(meas_gemv_n_kernel<float>, dim3((unsigned)totals[1]), dim3(256), 0, s, jobs_dev,
+                         njobs, part);
     HPT_LAUNCH_CHECK("meas_gemv_n_kernel");
-    dim3 g2((unsigned)std::min<int64_t>(ceil_div(max_rows, 256), 4096), (unsigned)njobs);
-    hipLaunchKernelGGL(meas_gemv_n_reduce, g2, dim3(256), 0, s, jobs_dev, part, stride_n);
+    hipLaunchKernelGGL(meas_gemv_n_reduce, dim3((unsigned)totals[3]), dim3(256), 0, s, jobs_dev, njobs, part);
     HPT_LAUNCH_CHECK("meas_gemv_n_reduce");
   }
-  {
-    dim3 grid((unsigned)ceil_div(max_ich, 4), (unsigned)max_nk, (unsigned)njobs);
+  if (totals[2] > 0) {
     if (is_double)
-      hipLaunchKernelGGL(meas_gemv_t_kernel<double>, grid, dim3(256), 0, s, jobs_dev, part,
-                         stride_t, max_ich);
+      hipLaunchKernelGGL(meas_gemv_t_kernel<double>, dim3((unsigned)totals[2]), dim3(256), 0, s, jobs_dev,
+                         njobs, part);
     else
-      hipLaunchKernelGGL(meas_gemv_t_kernel<float>, grid, dim3(256), 0, s, jobs_dev, part,
-                         stride_t, max_ich);
+      hipLaunchKernelGGL(meas_gemv_t_kernel<float>, dim3((unsigned)totals[2]), dim3(256), 0, s, jobs_dev,
+                         njobs, part);
     HPT_LAUNCH_CHECK("meas_gemv_t_kernel");
-    hipLaunchKernelGGL(meas_gemv_t_reduce, dim3(njobs), dim3(256), 0, s, jobs_dev, part,
-                       stride_t);
-    HPT_LAUNCH_CHECK("meas_gemv_t_reduce");
   }
+  hipLaunchKernelGGL(meas_gemv_t_reduce, dim3(njobs), dim3(256), 0, s, jobs_dev, part);
+  HPT_LAUNCH_CHECK("meas_gemv_t_reduce");
   return 0;
 }
 

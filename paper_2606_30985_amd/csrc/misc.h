@@ -60,9 +60,16 @@ struct MeasJob {
   double* y;           // scratch, O
   double* S;           // scratch, I * nk (used when O > 1)
   double* out;         // nk
+  // filled by meas_plan: block ranges of each stage and partial offsets
+  int64_t bk0, bn0, bt0, br0;
+  int64_t pn_off, pt_off;
 };
-int meas_contract(const MeasJob* jobs_dev, const MeasJob* jobs_host, int njobs, int is_double,
-                  double* part, int64_t part_cap, hipStream_t s);
+// meas_plan fills the block ranges and partial offsets of the host jobs and
+// returns the partial-buffer doubles they need; the caller then copies the
+// jobs to the device and calls meas_launch.
+int64_t meas_plan(MeasJob* jobs_host, int njobs, int64_t totals[4]);
+int meas_launch(const MeasJob* jobs_dev, int njobs, const int64_t totals[4], int is_double,
+                double* part, hipStream_t s);
 
 // normalise, sign continuity, damp, normalise; delta[i] = max |mn - mo|
 struct MeasNormJob {

@@ -1,0 +1,42 @@
+"""Write oracle trajectories used as expected values by the GPU parity tests.
+
+Calls only the CPU oracle (oracle/).  Usage: python tests/golden/make_golden.py NAME
+Each output file records the configuration it was computed with.
+"""
+
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle.network import Config  # noqa: E402
+from oracle.run import run  # noqa: E402
+
+CASES = {
+    # 4x4, centre (1,1), dt 0.05, 40 steps, chi_max 20, FP64, uniform-init BP, damping 0.5, tol 1e-10
+    "oracle_4x4_chi20": (dict(Lx=4, Ly=4, J=1.0, h=1.0, dt=0.05, chi_max=20, bp_alpha=0.5, bp_tol=1e-10), 40),
+    "oracle_4x4_chi40": (dict(Lx=4, Ly=4, J=1.0, h=1.0, dt=0.05, chi_max=40, bp_alpha=0.5, bp_tol=1e-10), 40),
+    "oracle_3x3_chi8": (dict(Lx=3, Ly=3, J=1.0, h=1.0, dt=0.05, chi_max=8, bp_alpha=0.5, bp_tol=1e-10), 20),
+}
+
+
+def main(name):
+    cfg, n = CASES[name]
+    t0 = time.time()
+
+    def cb(net, rec):
+        print(rec["step"], rec["C"], f"{time.time() - t0:.1f}s", flush=True)
+
+    recs, _ = run(Config(**cfg), n, callback=cb)
+    out = dict(config=cfg, nsteps=n, source="oracle/ (CPU FP64 restatement of the method)",
+               records=[{k: (v if not isinstance(v, float) or v == v else None) for k, v in r.items()}
+                        for r in recs])
+    with open(os.path.join(HERE, name + ".json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1])

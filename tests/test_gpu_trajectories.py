@@ -1,0 +1,67 @@
+"""Whole-path GPU trajectories C(t) against the CPU oracle."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import load_hpt
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _oracle(cfg, n):
+    from oracle.network import Config
+    from oracle.run import run
+    return run(Config(**cfg), n)[0]
+
+
+def _traj(hpt, cfg, n, **extra):
+    sim = hpt.Simulator(**cfg, **extra)
+    out = [sim.measure()]
+    for _ in range(n):
+        sim.step(1)
+        out.append(sim.measure())
+    sim.close()
+    return out
+
+
+@pytest.mark.parametrize("geom,chi,n", [((5, 1), 16, 12), ((2, 2), 16, 10), ((2, 3), 6, 10), ((4, 3), 5, 8), ((1, 4), 3, 8)])
+def test_small_lattices_fp64(geom, chi, n):
+    hpt = load_hpt()
+    cfg = dict(Lx=geom[0], Ly=geom[1], chi_max=chi, dt=0.1, J=1.0, h=0.8, bp_tol=1e-11)
+    ref = _oracle(cfg, n)
+    got = _traj(hpt, cfg, n)
+    for k in range(n + 1):
+        assert abs(got[k]["C"] - ref[k]["C"]) <= 1e-10, (k, got[k]["C"], ref[k]["C"])
+        assert got[k]["chi_live_max"] == ref[k]["chi_live_max"]
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"{name}.json not generated")
+    return json.load(open(path))
+
+
+def test_config1_chi20_fp64_vs_golden():
+    hpt = load_hpt()
+    g = _golden("oracle_4x4_chi20")
+    got = _traj(hpt, g["config"], g["nsteps"])
+    for k, rec in enumerate(g["records"]):
+        assert abs(got[k]["C"] - rec["C"]) <= 1e-10, (k, got[k]["C"], rec["C"])
+
+
+def test_config0_fp32_form_within_1e6():
+    # float32 tensors and MFMA contractions, float64 Cholesky / SVD / BP
+    # normalisation / Bethe: |dC| against the float64 oracle
+    hpt = load_hpt()
+    g = _golden("oracle_3x3_chi8")
+    cfg = dict(g["config"])
+    cfg["bp_tol"] = 1e-6
+    got = _traj(hpt, cfg, g["nsteps"], precision="fp32")
+    worst = max(abs(got[k]["C"] - rec["C"]) for k, rec in enumerate(g["records"]))
+    print("fp32 form worst |dC| on 3x3 chi 8:", worst)
+    assert worst <= 1e-6
