@@ -70,6 +70,8 @@ extern "C" {
 #define HPT_FLAG_PINV_CUT               (1u << 5)  /* an environment eigenvalue was dropped */
 #define HPT_FLAG_BETHE_ZERO             (1u << 6)  /* some vs_v or Z_e was exactly zero */
 #define HPT_FLAG_QR_FALLBACK            (1u << 7)  /* CholeskyQR2 failed, Householder used */
+#define HPT_FLAG_QR_RANK_DEFICIENT      (1u << 8)  /* a QR block had numerically dependent columns
+                                                      (deflated by the pivoted Cholesky) */
 
 typedef struct {
   int32_t Lx, Ly;          /* lattice, >= 1 each, Lx*Ly >= 2 */
@@ -92,7 +94,11 @@ typedef struct {
   int32_t meas_max_sweeps; /* <= 0 -> bp_max_sweeps */
   int32_t gauge_bp;        /* 1: run gauge BP after every layer (default); 0: skip */
   int32_t trap_sweeps;     /* trap rule threshold (Sec. "BP Fixed-Point Multiplicity"), 30 */
-  int32_t reserved[7];
+  double  qr_rank_tol;     /* CholeskyQR2 deflates a column when its remaining pivot is
+                              <= qr_rank_tol * max diag of the Gram matrix; 0: never
+                              deflate (a dependent column sends the block to Householder);
+                              < 0 (default): 0 in the FP64 form, 1e-12 in the FP32 form */
+  int32_t reserved[6];
 } hpt_config;
 
 typedef struct {

@@ -46,6 +46,9 @@ struct GemmDesc {
   const T* B; int64_t ldb, sBz, sBr; int tB;
   void* C; int64_t ldc, sCz; int c_double;
   double alpha, beta;
+  int sym;   // op(B) = op(A)^T and M == N: only tiles on or above the diagonal
+             // are computed, the result is mirrored (a SYRK)
+  int acc64; // float inputs multiplied and accumulated in float64 (f64 MFMA)
 };
 template <typename T>
 int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s);

@@ -95,9 +95,11 @@ struct hpt_sim {
   double* meas_scr;
   std::vector<hpt::BondSlot> slots;
   // CholeskyQR2 scratch
-  double *G1, *R1, *Ri1, *G2, *R2, *Ri2;
+  double *G1, *R1, *Ri1, *G2, *R2, *Ri2, *W1;
   float* Ri32;
-  int* info;
+  int* sel;
+  int* info;            // [0] Cholesky info, [1] pivoted-Cholesky rank
+  double cfg_qr_tol;
   // small device arrays
   double* bethe_x;      // N + nb values
   double* res;          // 8 doubles

@@ -86,6 +86,7 @@ int validate(const hpt_config* c) {
   if (!(c->eps_cut >= 0.0) || !(c->eps_pinv >= 0.0)) return HPT_EINVAL;
   if (!(c->bp_alpha > 0.0 && c->bp_alpha <= 1.0) || !(c->bp_tol > 0.0) || c->bp_max_sweeps < 1) return HPT_EINVAL;
   if (c->meas_alpha > 1.0) return HPT_EINVAL;
+  if (!(c->qr_rank_tol < 1.0)) return HPT_EINVAL;
   if (c->bp_init != HPT_BP_UNIFORM && c->bp_init != HPT_BP_WARM) return HPT_EINVAL;
   // the storage of one interior site must stay addressable with 64-bit offsets
   // and its element count below 2^40
@@ -210,7 +211,7 @@ void make_carve(const hpt_config& c, Carve& cv) {
   cv.max_colour_bonds = mcb;
   cv.slot_bytes = slot_layout(C, fp32, nullptr, nullptr);
   cv.slots = off; off = align_up(off + cv.slot_bytes * mcb);
-  cv.chol = off; off = align_up(off + 6 * n4 * n4 * 8 + n4 * n4 * 4 + 4 * n4 * 8 + 256);
+  cv.chol = off; off = align_up(off + 7 * n4 * n4 * 8 + n4 * n4 * 4 + 4 * n4 * 8 + n4 * 4 + 256);
   cv.small = off; off = align_up(off + (uint64_t)(N + nb + 64) * 8 + 2ull * nb * 8 + 16 * 8 +
                                  (uint64_t)mcb * sizeof(BondCore));
   cv.jobs_bytes = 4ull << 20;
@@ -316,6 +317,20 @@ int matmul(hpt_sim* s, int64_t m, int64_t n, int64_t k, const T* A, int64_t lda,
   return 0;
 }
 
+// G (n x n, double) = X^T X for X (m x n, column-major), as a SYRK
+template <typename T>
+int gram(hpt_sim* s, int64_t n, int64_t m, const T* X, int64_t ldx, double* G) {
+  GemmDesc<T> d{};
+  d.M = (int)n; d.N = (int)n; d.K = (int)m; d.R = 1; d.Z = 1;
+  d.A = X; d.lda = ldx; d.tA = 1;
+  d.B = X; d.ldb = ldx; d.tB = 0;
+  d.C = G; d.ldc = n; d.c_double = 1;
+  d.alpha = 1.0; d.beta = 0.0; d.sym = 1;
+  d.acc64 = 1;  // products of float data accumulated in float64
+  KR(gemm<T>(d, s->part, s->cv.part_cap, s->stream));
+  return 0;
+}
+
 template <typename T> T* psi_of(hpt_sim* s, int v) { return (T*)s->sites[v].psi; }
 
 void site_dims(hpt_sim* s, int v, int64_t* dims) {
@@ -417,51 +432,66 @@ int phase_a_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, uint32_t& 
   bool use_chol = s->cfg.qr_mode == HPT_QR_ADAPTIVE && m >= (int64_t)s->cfg.chol_min_ratio * n &&
                   n >= s->cfg.chol_min_cols;
   if (use_chol) {
-    // CholeskyQR2: G1 = X^T X, R1 = chol(G1), Q1 = X R1^{-1}, G2 = Q1^T Q1, R2 = chol(G2)
-    RC(matmul<T>(s, n, n, m, psi, m, 1, psi, m, 0, s->G1, n, 1));
-    CholJob cj{s->G1, n, n, s->R1, n, s->info, nullptr};
-    CholJob* cjd;
-    RC(stage(s, &cj, 1, &cjd));
-    KR(launch_cholesky(cjd, 1, 1e-13, s->stream));
-    int info = 0;
-    HPT_HIP(hipMemcpyAsync(s->hscratch, s->info, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    // rank-revealing CholeskyQR2: G1 = X^T X; pivoted Cholesky R1 (rank r,
+    // exact structural zeros deflated); Q1 = X W1 with W1 = E_sel R1sel^{-1};
+    // G2 = Q1^T Q1 = R2^T R2.  Then X = (Q1 R2^{-1}) (R2 R1) and Q = X W1 R2^{-1}.
+    RC(gram<T>(s, n, m, psi, m, s->G1));
+    // with tolerance 0 the pivoted factorisation stops at the first pivot
+    // below 1e-13 of the largest and the block goes to Householder instead
+    const bool deflate = s->cfg_qr_tol > 0.0;
+    PivCholJob pj{s->G1, n, n, s->R1, n, s->sel, s->info + 1, deflate ? s->cfg_qr_tol : 1e-13};
+    PivCholJob* pjd;
+    RC(stage(s, &pj, 1, &pjd));
+    KR(launch_piv_cholesky(pjd, 1, s->stream));
+    HPT_HIP(hipMemcpyAsync(s->hscratch, s->info + 1, sizeof(int), hipMemcpyDeviceToHost, s->stream));
     RC(sync_stream(s));
-    std::memcpy(&info, s->hscratch, sizeof(int));
-    if (info == 0) {
-      TriInvJob tj{s->R1, n, n, s->Ri1, n, nullptr};
+    int r = 0;
+    std::memcpy(&r, s->hscratch, sizeof(int));
+    if (r >= 1 && (deflate || r == n)) {
+      if (r < n) flags |= HPT_FLAG_QR_RANK_DEFICIENT;
+      SelJob g0{0, s->R1, n, s->G2, r, s->sel, r, n};
+      SelJob* sjd;
+      RC(stage(s, &g0, 1, &sjd));
+      KR(launch_sel(sjd, 1, s->stream));
+      TriInvJob tj{s->G2, r, r, s->Ri1, r, nullptr};
       TriInvJob* tjd;
       RC(stage(s, &tj, 1, &tjd));
       KR(launch_tri_inverse(tjd, 1, s->stream));
-      const T* Ri;
+      SelJob g1{1, s->Ri1, r, s->W1, n, s->sel, r, n};
+      RC(stage(s, &g1, 1, &sjd));
+      KR(launch_sel(sjd, 1, s->stream));
+      const T* W1;
       if (sizeof(T) == 4) {
-        KR(launch_d2f(s->Ri1, s->Ri32, (int64_t)n * n, s->stream));
-        Ri = (const T*)s->Ri32;
+        KR(launch_d2f(s->W1, s->Ri32, (int64_t)n * r, s->stream));
+        W1 = (const T*)s->Ri32;
       } else {
-        Ri = (const T*)s->Ri1;
+        W1 = (const T*)s->W1;
       }
       T* Q1 = (T*)s->t[0];
-      RC(matmul<T>(s, m, n, n, psi, m, 0, Ri, n, 0, Q1, m, 0));
-      RC(matmul<T>(s, n, n, m, Q1, m, 1, Q1, m, 0, s->G2, n, 1));
-      CholJob cj2{s->G2, n, n, s->R2, n, s->info, nullptr};
+      RC(matmul<T>(s, m, r, n, psi, m, 0, W1, n, 0, Q1, m, 0));
+      RC(gram<T>(s, r, m, Q1, m, s->G2));
+      CholJob cj2{s->G2, r, r, s->R2, r, s->info, nullptr};
+      CholJob* cjd;
       RC(stage(s, &cj2, 1, &cjd));
       KR(launch_cholesky(cjd, 1, 1e-13, s->stream));
       HPT_HIP(hipMemcpyAsync(s->hscratch, s->info, sizeof(int), hipMemcpyDeviceToHost, s->stream));
       RC(sync_stream(s));
+      int info = 0;
       std::memcpy(&info, s->hscratch, sizeof(int));
       if (info == 0) {
-        TriInvJob tj2{s->R2, n, n, s->Ri2, n, nullptr};
+        TriInvJob tj2{s->R2, r, r, s->Ri2, r, nullptr};
         RC(stage(s, &tj2, 1, &tjd));
         KR(launch_tri_inverse(tjd, 1, s->stream));
-        // R = R2 R1 (ld 4 chi_max), Rinv = R1^{-1} R2^{-1}
+        // R = R2 R1 (r x n, ld 4 chi_max), Rinv = W1 R2^{-1} (n x r)
         SmallGemmJob gj[2];
         std::memset(gj, 0, sizeof(gj));
-        gj[0] = SmallGemmJob{n, n, n, nullptr, nullptr, nullptr, s->R2, n, 0, s->R1, n, 0, sl.R[i], ldR, 1.0, 0.0, nullptr};
-        gj[1] = SmallGemmJob{n, n, n, nullptr, nullptr, nullptr, s->Ri1, n, 0, s->Ri2, n, 0, sl.Rinv[i], ldR, 1.0, 0.0, nullptr};
+        gj[0] = SmallGemmJob{r, n, r, nullptr, nullptr, nullptr, s->R2, r, 0, s->R1, n, 0, sl.R[i], ldR, 1.0, 0.0, nullptr};
+        gj[1] = SmallGemmJob{n, r, r, nullptr, nullptr, nullptr, s->W1, n, 0, s->Ri2, r, 0, sl.Rinv[i], ldR, 1.0, 0.0, nullptr};
         SmallGemmJob* gjd;
         RC(stage(s, gj, 2, &gjd));
         KR(launch_small_gemm(gjd, 2, s->stream));
         P.chol = 1;
-        P.k = n;
+        P.k = r;
       }
     }
     if (!P.chol) flags |= HPT_FLAG_QR_FALLBACK;
@@ -674,7 +704,7 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
       for (int i = 0; i < 2; ++i) {
         if (!bc.chol[i]) continue;
         const int n = 4 * bc.chi_cut;
-        SmallGemmJob j{n, 0, n, nullptr, &cd[q].n4, nullptr, bc.Rinv[i], ldR, 0, bc.Mp[i], bc.k[i], 0,
+        SmallGemmJob j{n, 0, bc.k[i], nullptr, &cd[q].n4, nullptr, bc.Rinv[i], ldR, 0, bc.Mp[i], bc.k[i], 0,
                        bc.W[i], n, 1.0, 0.0, nullptr};
         gj.push_back(j);
       }
@@ -1090,6 +1120,7 @@ int hpt_config_default(hpt_config* c) {
   c->meas_max_sweeps = 0;
   c->gauge_bp = 1;
   c->trap_sweeps = 30;
+  c->qr_rank_tol = -1.0;
   return HPT_OK;
 }
 
@@ -1178,8 +1209,10 @@ int hpt_create(const hpt_config* cfg, void* arena, uint64_t arena_bytes, void* h
     s->G2 = (double*)c; c += sz;
     s->R2 = (double*)c; c += sz;
     s->Ri2 = (double*)c; c += sz;
+    s->W1 = (double*)c; c += sz;
     s->Ri32 = (float*)c; c += n4 * n4 * 4;
     c += 4 * n4 * 8;
+    s->sel = (int*)c; c += n4 * 4;
     s->info = (int*)c;
   }
   {
@@ -1204,6 +1237,10 @@ int hpt_create(const hpt_config* cfg, void* arena, uint64_t arena_bytes, void* h
     return HPT_EHIP;
   }
   make_gate_tables(s);
+  // qr_rank_tol < 0: float64 form keeps CholeskyQR2 exact (any dependent
+  // column sends the block to Householder), float32 form deflates columns
+  // whose remaining pivot is below the float32 resolution of the Gram matrix
+  s->cfg_qr_tol = cfg->qr_rank_tol >= 0.0 ? cfg->qr_rank_tol : (s->fp32 ? 1e-12 : 0.0);
   r = s->fp32 ? reset_t<float>(s) : reset_t<double>(s);
   if (r) {
     hpt_destroy(s);

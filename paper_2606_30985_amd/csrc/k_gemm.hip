@@ -9,6 +9,8 @@
 // contiguous axis of each operand.  The reduction space (batch r, k-chunks)
 // can be split across workgroups; partial tiles are then summed in float64
 // by a second, deterministic kernel.
+#include <cstdlib>
+
 #include "common.h"
 
 namespace hpt {
@@ -27,24 +29,67 @@ template <typename T> struct Acc;
 template <> struct Acc<double> { typedef d4 type; };
 template <> struct Acc<float> { typedef f4 type; };
 
+__device__ inline void tile_of(int64_t bx, int tiles_m, int tiles_n, int sym, int& z, int& tm, int& tn) {
+  if (!sym) {
+    const int64_t tiles = (int64_t)tiles_m * tiles_n;
+    z = (int)(bx / tiles);
+    const int64_t t = bx % tiles;
+    tm = (int)(t % tiles_m);
+    tn = (int)(t / tiles_m);
+    return;
+  }
+  // upper-triangular tiles (tm <= tn), column by column
+  const int64_t tiles = (int64_t)tiles_m * (tiles_m + 1) / 2;
+  z = (int)(bx / tiles);
+  int64_t t = bx % tiles;
+  int c = 0;
+  while (t > c) {
+    t -= c + 1;
+    ++c;
+  }
+  tm = (int)t;
+  tn = c;
+}
+
+// store one result element; for a symmetric product also its mirror
 template <typename T>
+__device__ inline void put(const GemmDesc<T>& d, int z, int gi, int gj, double v, int splits,
+                           int split, double* part) {
+  if (d.sym && gi > gj) return;
+  if (splits > 1) {
+    part[(((int64_t)split * d.Z + z) * d.N + gj) * d.M + gi] = v;
+    return;
+  }
+  for (int rep = 0; rep < (d.sym && gi != gj ? 2 : 1); ++rep) {
+    const int r = rep ? gj : gi, c = rep ? gi : gj;
+    const int64_t off = (int64_t)z * d.sCz + r + (int64_t)c * d.ldc;
+    if (d.c_double) {
+      double* C = (double*)d.C;
+      C[off] = d.alpha * v + (d.beta != 0.0 ? d.beta * C[off] : 0.0);
+    } else {
+      T* C = (T*)d.C;
+      C[off] = (T)(d.alpha * v + (d.beta != 0.0 ? d.beta * (double)C[off] : 0.0));
+    }
+  }
+}
+
+// T: storage type of A and B; TC: MFMA type (T, or double for float inputs
+// whose products must be accumulated in float64)
+template <typename T, typename TC>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc<T> d, int tiles_m, int tiles_n,
                                                    int splits, int64_t chunks_per_r,
                                                    double* part) {
-  typedef typename Acc<T>::type acc_t;
-  __shared__ T As[TK][TM + PAD];
-  __shared__ T Bs[TK][TN + PAD];
+  typedef typename Acc<TC>::type acc_t;
+  __shared__ TC As[TK][TM + PAD];
+  __shared__ TC Bs[TK][TN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
 
-  const int64_t tiles = (int64_t)tiles_m * tiles_n;
-  const int64_t bx = blockIdx.x;
-  const int z = (int)(bx / tiles);
-  const int64_t t = bx % tiles;
-  const int tm = (int)(t % tiles_m), tn = (int)(t / tiles_m);
+  int z, tm, tn;
+  tile_of(blockIdx.x, tiles_m, tiles_n, d.sym, z, tm, tn);
   const int split = blockIdx.y;
 
   const int64_t total = (int64_t)d.R * chunks_per_r;
@@ -73,8 +118,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc<T> d, int tiles_m, i
       for (int q = 0; q < 4; ++q) {
         const int k = (tid >> 6) + 4 * q;
         const int gk = k0 + k;
-        T v = 0;
-        if (gi < d.M && gk < d.K) v = Ar[gi + (int64_t)gk * d.lda];
+        TC v = 0;
+        if (gi < d.M && gk < d.K) v = (TC)Ar[gi + (int64_t)gk * d.lda];
         As[k][i] = v;
       }
     } else {
@@ -83,8 +128,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc<T> d, int tiles_m, i
       for (int q = 0; q < 4; ++q) {
         const int i = (tid >> 4) + 16 * q;
         const int gi = row0 + i;
-        T v = 0;
-        if (gi < d.M && gk < d.K) v = Ar[gk + (int64_t)gi * d.lda];
+        TC v = 0;
+        if (gi < d.M && gk < d.K) v = (TC)Ar[gk + (int64_t)gi * d.lda];
         As[k][i] = v;
       }
     }
@@ -95,8 +140,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc<T> d, int tiles_m, i
       for (int q = 0; q < 4; ++q) {
         const int j = (tid >> 4) + 16 * q;
         const int gj = col0 + j;
-        T v = 0;
-        if (gj < d.N && gk < d.K) v = Br[gk + (int64_t)gj * d.ldb];
+        TC v = 0;
+        if (gj < d.N && gk < d.K) v = (TC)Br[gk + (int64_t)gj * d.ldb];
         Bs[k][j] = v;
       }
     } else {
@@ -105,8 +150,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc<T> d, int tiles_m, i
       for (int q = 0; q < 4; ++q) {
         const int k = (tid >> 6) + 4 * q;
         const int gk = k0 + k;
-        T v = 0;
-        if (gj < d.N && gk < d.K) v = Br[gj + (int64_t)gk * d.ldb];
+        TC v = 0;
+        if (gj < d.N && gk < d.K) v = (TC)Br[gj + (int64_t)gk * d.ldb];
         Bs[k][j] = v;
       }
     }
@@ -114,40 +159,30 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc<T> d, int tiles_m, i
 #pragma unroll
     for (int kk = 0; kk < TK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
-      T a0 = As[kr][wr * 32 + (lane & 15)];
-      T a1 = As[kr][wr * 32 + 16 + (lane & 15)];
-      T b0 = Bs[kr][wc * 32 + (lane & 15)];
-      T b1 = Bs[kr][wc * 32 + 16 + (lane & 15)];
-      acc[0][0] = mfma_op(a0, b0, acc[0][0]);
-      acc[0][1] = mfma_op(a0, b1, acc[0][1]);
-      acc[1][0] = mfma_op(a1, b0, acc[1][0]);
-      acc[1][1] = mfma_op(a1, b1, acc[1][1]);
+      TC a0 = As[kr][wr * 32 + (lane & 15)];
+      TC a1 = As[kr][wr * 32 + 16 + (lane & 15)];
+      TC b0 = Bs[kr][wc * 32 + (lane & 15)];
+      TC b1 = Bs[kr][wc * 32 + 16 + (lane & 15)];
+      // operands swapped (B fragment first): the MFMA then produces C^T
+      // blocks whose lane index runs along C's contiguous row axis
+      acc[0][0] = mfma_op(b0, a0, acc[0][0]);
+      acc[0][1] = mfma_op(b1, a0, acc[0][1]);
+      acc[1][0] = mfma_op(b0, a1, acc[1][0]);
+      acc[1][1] = mfma_op(b1, a1, acc[1][1]);
     }
     __syncthreads();
   }
 
-  // write out: block (bi, bj), register e -> col lane%16 and row
+  // write out: block (bi, bj), register e -> row lane%16 and column
   // 4*(lane/16)+e for the f32 MFMA, lane/16 + 4*e for the f64 MFMA
   for (int bi = 0; bi < 2; ++bi)
     for (int bj = 0; bj < 2; ++bj)
       for (int e = 0; e < 4; ++e) {
-        const int rloc = sizeof(T) == 8 ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e;
-        const int gi = row0 + wr * 32 + bi * 16 + rloc;
-        const int gj = col0 + wc * 32 + bj * 16 + (lane & 15);
+        const int cloc = sizeof(TC) == 8 ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e;
+        const int gi = row0 + wr * 32 + bi * 16 + (lane & 15);
+        const int gj = col0 + wc * 32 + bj * 16 + cloc;
         if (gi >= d.M || gj >= d.N) continue;
-        const double v = (double)acc[bi][bj][e];
-        if (splits > 1) {
-          part[(((int64_t)split * d.Z + z) * d.N + gj) * d.M + gi] = v;
-        } else {
-          const int64_t off = (int64_t)z * d.sCz + gi + (int64_t)gj * d.ldc;
-          if (d.c_double) {
-            double* C = (double*)d.C;
-            C[off] = d.alpha * v + (d.beta != 0.0 ? d.beta * C[off] : 0.0);
-          } else {
-            T* C = (T*)d.C;
-            C[off] = (T)(d.alpha * v + (d.beta != 0.0 ? d.beta * (double)C[off] : 0.0));
-          }
-        }
+        put<T>(d, z, gi, gj, (double)acc[bi][bj][e], splits, split, part);
       }
 }
 
@@ -166,11 +201,8 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(GemmDesc<T> d, int tiles_
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int64_t tiles = (int64_t)tiles_m * tiles_n;
-  const int64_t bx = blockIdx.x;
-  const int z = (int)(bx / tiles);
-  const int64_t t = bx % tiles;
-  const int tm = (int)(t % tiles_m), tn = (int)(t / tiles_m);
+  int z, tm, tn;
+  tile_of(blockIdx.x, tiles_m, tiles_n, d.sym, z, tm, tn);
   const int split = blockIdx.y;
   const int64_t total = (int64_t)d.R * chunks_per_r;
   const int64_t per = (total + splits - 1) / splits;
@@ -246,7 +278,7 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(GemmDesc<T> d, int tiles_
         for (int i = 0; i < 4; ++i) a[i] = As[buf][kr][wr * 64 + i * 16 + (lane & 15)];
         for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kr][wc * 64 + j * 16 + (lane & 15)];
         for (int i = 0; i < 4; ++i)
-          for (int j = 0; j < 4; ++j) acc[i][j] = mfma_op(a[i], b[j], acc[i][j]);
+          for (int j = 0; j < 4; ++j) acc[i][j] = mfma_op(b[j], a[i], acc[i][j]);
       }
       if (more) store(buf ^ 1);
       __syncthreads();
@@ -257,23 +289,11 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(GemmDesc<T> d, int tiles_
   for (int bi = 0; bi < 4; ++bi)
     for (int bj = 0; bj < 4; ++bj)
       for (int e = 0; e < 4; ++e) {
-        const int rloc = sizeof(T) == 8 ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e;
-        const int gi = row0 + wr * 64 + bi * 16 + rloc;
-        const int gj = col0 + wc * 64 + bj * 16 + (lane & 15);
+        const int cloc = sizeof(T) == 8 ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e;
+        const int gi = row0 + wr * 64 + bi * 16 + (lane & 15);
+        const int gj = col0 + wc * 64 + bj * 16 + cloc;
         if (gi >= d.M || gj >= d.N) continue;
-        const double v = (double)acc[bi][bj][e];
-        if (splits > 1) {
-          part[(((int64_t)split * d.Z + z) * d.N + gj) * d.M + gi] = v;
-        } else {
-          const int64_t off = (int64_t)z * d.sCz + gi + (int64_t)gj * d.ldc;
-          if (d.c_double) {
-            double* C = (double*)d.C;
-            C[off] = d.alpha * v + (d.beta != 0.0 ? d.beta * C[off] : 0.0);
-          } else {
-            T* C = (T*)d.C;
-            C[off] = (T)(d.alpha * v + (d.beta != 0.0 ? d.beta * (double)C[off] : 0.0));
-          }
-        }
+        put<T>(d, z, gi, gj, (double)acc[bi][bj][e], splits, split, part);
       }
 }
 
@@ -286,16 +306,10 @@ __global__ void gemm_reduce_kernel(GemmDesc<T> d, int splits, const double* part
     const int z = (int)(idx / mn);
     const int64_t e = idx % mn;
     const int gi = (int)(e % d.M), gj = (int)(e / d.M);
+    if (d.sym && gi > gj) continue;
     double s = 0.0;
     for (int k = 0; k < splits; ++k) s += part[(((int64_t)k * d.Z + z) * d.N + gj) * d.M + gi];
-    const int64_t off = (int64_t)z * d.sCz + gi + (int64_t)gj * d.ldc;
-    if (d.c_double) {
-      double* C = (double*)d.C;
-      C[off] = d.alpha * s + (d.beta != 0.0 ? d.beta * C[off] : 0.0);
-    } else {
-      T* C = (T*)d.C;
-      C[off] = (T)(d.alpha * s + (d.beta != 0.0 ? d.beta * (double)C[off] : 0.0));
-    }
+    put<T>(d, z, gi, gj, s, 1, 0, nullptr);
   }
 }
 
@@ -358,10 +372,16 @@ template <typename T>
 int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.Z <= 0) return 0;
   if (d.K <= 0 || d.R <= 0) return -1;  // callers never ask for an empty reduction
-  const bool big = d.M >= 96 && d.N >= 96;
+  // 64 x 64 tiles; HPT_GEMM_TILE=128 selects the 128 x 128 variant (tuning)
+  static const int forced = [] {
+    const char* e = getenv("HPT_GEMM_TILE");
+    return e ? atoi(e) : 0;
+  }();
+  const bool big = !d.acc64 && forced == 128;
   const int tile = big ? BT : TM;
   const int tiles_m = (int)ceil_div(d.M, tile), tiles_n = (int)ceil_div(d.N, tile);
-  const int64_t tiles = (int64_t)tiles_m * tiles_n * d.Z;
+  if (d.sym && d.M != d.N) return -1;
+  const int64_t tiles = (d.sym ? (int64_t)tiles_m * (tiles_m + 1) / 2 : (int64_t)tiles_m * tiles_n) * d.Z;
   const int64_t chunks_per_r = ceil_div(d.K, TK);
   const int64_t total = chunks_per_r * d.R;
   // split the reduction until the grid covers the chip several times over,
@@ -379,11 +399,14 @@ int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
     }
     HPT_HIP(hipEventRecord(g_prof.ev[2 * g_prof.n], s));
   }
-  if (big)
+  if (d.acc64 && sizeof(T) == 4)
+    hipLaunchKernelGGL((gemm_kernel<T, double>), grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
+                       chunks_per_r, part);
+  else if (big)
     hipLaunchKernelGGL(gemm_big_kernel<T>, grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
                        chunks_per_r, part);
   else
-    hipLaunchKernelGGL(gemm_kernel<T>, grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
+    hipLaunchKernelGGL((gemm_kernel<T, T>), grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
                        chunks_per_r, part);
   HPT_LAUNCH_CHECK("gemm_kernel");
   if (prof) {
@@ -391,7 +414,7 @@ int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
     g_prof.n++;
     g_prof.launches += 1;
     const double M = d.M, N = d.N, K = d.K, R = d.R, Z = d.Z;
-    g_prof.flops += 2.0 * M * N * K * R * Z;
+    g_prof.flops += (d.sym ? 1.0 : 2.0) * M * N * K * R * Z;  // algorithmic: a SYRK does half
     const double za = d.sAz ? Z : 1.0, zb = d.sBz ? Z : 1.0;
     const double ra = d.sAr ? R : 1.0, rb = d.sBr ? R : 1.0;
     g_prof.bytes += sizeof(T) * (M * K * ra * za + K * N * rb * zb) +

@@ -411,6 +411,119 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(const CholJob* jobs, dou
   if (tid == 0) *job.info = 0;
 }
 
+// Diagonal-pivoted Cholesky (rank-revealing CholeskyQR first pass): at each
+// step the column with the largest remaining pivot is chosen; stop when it
+// falls to tau times the largest diagonal entry.  One wave per column for the
+// row update, lanes over the previous rows.
+__global__ __launch_bounds__(1024) void piv_cholesky_kernel(const PivCholJob* jobs) {
+  const PivCholJob job = jobs[blockIdx.x];
+  const int n = job.n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  double* R = job.R;
+  const int ldr = job.ldr;
+  __shared__ double d[1024];
+  __shared__ int used[1024];
+  __shared__ double wbest[16];
+  __shared__ int widx[16];
+  __shared__ int s_p, s_stop;
+  __shared__ double s_rjj, s_dmax;
+  for (int i = tid; i < n; i += blockDim.x) {
+    d[i] = job.G[i + (int64_t)i * job.ldg];
+    used[i] = 0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) m = fmax(m, d[i]);
+    s_dmax = m;
+  }
+  __syncthreads();
+  int j = 0;
+  for (; j < n; ++j) {
+    // argmax of the remaining pivots (ties -> smaller index)
+    double best = -1.0;
+    int bi = n;
+    for (int i = tid; i < n; i += blockDim.x)
+      if (!used[i] && (d[i] > best || (d[i] == best && i < bi))) {
+        best = d[i];
+        bi = i;
+      }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      wbest[wave] = best;
+      widx[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double b = -1.0;
+      int p = n;
+      for (int w = 0; w < nw; ++w)
+        if (wbest[w] > b || (wbest[w] == b && widx[w] < p)) {
+          b = wbest[w];
+          p = widx[w];
+        }
+      s_stop = !(p < n && b > job.tau * s_dmax && b > 0.0);
+      s_p = p;
+      s_rjj = s_stop ? 0.0 : sqrt(b);
+      if (!s_stop) job.sel[j] = p;
+    }
+    __syncthreads();
+    if (s_stop) break;
+    const int p = s_p;
+    const double rjj = s_rjj;
+    const double* Rp = R + (int64_t)p * ldr;
+    for (int c = wave; c < n; c += nw) {
+      double* Rc = R + (int64_t)c * ldr;
+      if (c == p) {
+        if (lane == 0) Rc[j] = rjj;
+      } else if (used[c]) {
+        if (lane == 0) Rc[j] = 0.0;
+      } else {
+        double part = 0.0;
+        for (int k = lane; k < j; k += 64) part += Rp[k] * Rc[k];
+        part = wave_sum(part);
+        if (lane == 0) {
+          const double v = (job.G[p + (int64_t)c * job.ldg] - part) / rjj;
+          Rc[j] = v;
+          d[c] -= v * v;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) used[p] = 1;
+    __syncthreads();
+  }
+  if (tid == 0) *job.rank = j;
+}
+
+__global__ void sel_kernel(const SelJob* jobs) {
+  const SelJob job = jobs[blockIdx.x];
+  const int r = job.r, n = job.n;
+  if (job.mode == 0) {
+    for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) {
+      const int i = idx % r, k = idx / r;
+      job.out[i + (int64_t)k * job.ldout] = job.in[i + (int64_t)job.sel[k] * job.ldin];
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < n * r; idx += blockDim.x) {
+      const int row = idx % n, c = idx / n;
+      job.out[row + (int64_t)c * job.ldout] = 0.0;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) {
+      const int k = idx % r, c = idx / r;
+      job.out[job.sel[k] + (int64_t)c * job.ldout] = job.in[k + (int64_t)c * job.ldin];
+    }
+  }
+}
+
 // Inverse of an upper-triangular R: Y = (R^T)^{-1} is lower triangular and
 // column c of Y follows from forward substitution with the columns of R
 // (contiguous reads); one wave per column, lanes over the inner index.
@@ -499,6 +612,20 @@ int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s) {
   if (njobs <= 0) return 0;
   hipLaunchKernelGGL(tri_inverse_kernel, dim3(njobs), dim3(1024), 0, s, jobs);
   HPT_LAUNCH_CHECK("tri_inverse_kernel");
+  return 0;
+}
+
+int launch_piv_cholesky(const PivCholJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  hipLaunchKernelGGL(piv_cholesky_kernel, dim3(njobs), dim3(1024), 0, s, jobs);
+  HPT_LAUNCH_CHECK("piv_cholesky_kernel");
+  return 0;
+}
+
+int launch_sel(const SelJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  hipLaunchKernelGGL(sel_kernel, dim3(njobs), dim3(256), 0, s, jobs);
+  HPT_LAUNCH_CHECK("sel_kernel");
   return 0;
 }
 

@@ -49,6 +49,27 @@ struct CholJob {
   const int* gate;     // skip when *gate == 0 (null = always run)
 };
 
+// Cholesky with diagonal pivoting of an n x n PSD Gram matrix, stopped when
+// the largest remaining pivot is <= tau * max diag(G).  Row j of R (original
+// column order) is written for j < rank; sel[j] is the column chosen at step
+// j, so R[:, sel] is upper triangular.  *rank receives the number of steps.
+struct PivCholJob {
+  const double* G; int ldg; int n;
+  double* R; int ldr;
+  int* sel;
+  int* rank;
+  double tau;
+};
+
+// Rsel[i, k] = R[i, sel[k]] (gather, r x r) or W[sel[k], c] = Rs[k, c] with
+// the other rows of W zero (scatter, n x r).
+struct SelJob {
+  int mode;            // 0 gather, 1 scatter
+  const double* in; int ldin;
+  double* out; int ldout;
+  const int* sel; int r, n;
+};
+
 // Inverse of an upper-triangular n x n matrix.
 struct TriInvJob {
   const double* R; int ldr; int n;
@@ -74,6 +95,8 @@ int launch_householder(const QrJob<T>* jobs, int njobs, hipStream_t s);
 int launch_jacobi_svd(const SvdJob* jobs, int njobs, hipStream_t s);
 int launch_cholesky(const CholJob* jobs, int njobs, double rel_tol, hipStream_t s);
 int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s);
+int launch_piv_cholesky(const PivCholJob* jobs, int njobs, hipStream_t s);
+int launch_sel(const SelJob* jobs, int njobs, hipStream_t s);
 int launch_small_gemm(const SmallGemmJob* jobs, int njobs, hipStream_t s);
 
 }  // namespace hpt

@@ -30,6 +30,7 @@ FLAGS = {
     "PINV_CUT": 1 << 5,
     "BETHE_ZERO": 1 << 6,
     "QR_FALLBACK": 1 << 7,
+    "QR_RANK_DEFICIENT": 1 << 8,
 }
 
 
@@ -45,7 +46,8 @@ class HptConfig(ctypes.Structure):
         ("bp_max_sweeps", ctypes.c_int32), ("bp_init", ctypes.c_int32),
         ("meas_alpha", ctypes.c_double), ("meas_tol", ctypes.c_double),
         ("meas_max_sweeps", ctypes.c_int32), ("gauge_bp", ctypes.c_int32),
-        ("trap_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+        ("trap_sweeps", ctypes.c_int32), ("qr_rank_tol", ctypes.c_double),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 

@@ -65,3 +65,15 @@ def test_config0_fp32_form_within_1e6():
     worst = max(abs(got[k]["C"] - rec["C"]) for k, rec in enumerate(g["records"]))
     print("fp32 form worst |dC| on 3x3 chi 8:", worst)
     assert worst <= 1e-6
+
+
+def test_config1_chi20_fp32_form():
+    # the float32 form on 4x4 chi 20: |dC| against the float64 oracle, first 30 layers
+    hpt = load_hpt()
+    g = _golden("oracle_4x4_chi20")
+    cfg = dict(g["config"])
+    cfg["bp_tol"] = 1e-6
+    got = _traj(hpt, cfg, 30, precision="fp32")
+    worst = max(abs(got[k]["C"] - g["records"][k]["C"]) for k in range(31))
+    print("fp32 form worst |dC| on 4x4 chi 20 (30 layers):", worst)
+    assert worst <= 1e-5
