@@ -83,7 +83,8 @@ typedef struct {
   int32_t chol_min_ratio;  /* CholeskyQR2 needs rows >= chol_min_ratio * cols (default 2) */
   int32_t chol_min_cols;   /* ... and cols >= chol_min_cols (default 16); the paper's
                               rule (Sec. "Adaptive QR Decomposition") is ratio 150, cols 150 */
-  double  eps_cut;         /* truncation cutoff relative to s_0 (Eq. truncation), 1e-11 */
+  double  eps_cut;         /* truncation cutoff relative to s_0 (Eq. truncation); < 0
+                              (default): 1e-11 in the FP64 form, 1e-7 in the FP32 form */
   double  eps_pinv;        /* environment eigenvalue cutoff relative to the largest, 1e-12 */
   double  bp_alpha;        /* damping (Eq. damping), 0.5 */
   double  bp_tol;          /* max |change| stopping rule (Eq. bp_tol), 1e-10 */

@@ -83,7 +83,7 @@ int validate(const hpt_config* c) {
   if (c->precision != HPT_FP64 && c->precision != HPT_FP32_MFMA) return HPT_EINVAL;
   if (c->qr_mode != HPT_QR_ADAPTIVE && c->qr_mode != HPT_QR_HOUSEHOLDER) return HPT_EINVAL;
   if (c->chol_min_ratio < 1 || c->chol_min_cols < 1) return HPT_EINVAL;
-  if (!(c->eps_cut >= 0.0) || !(c->eps_pinv >= 0.0)) return HPT_EINVAL;
+  if (!(c->eps_cut < 1.0) || !(c->eps_pinv >= 0.0)) return HPT_EINVAL;
   if (!(c->bp_alpha > 0.0 && c->bp_alpha <= 1.0) || !(c->bp_tol > 0.0) || c->bp_max_sweeps < 1) return HPT_EINVAL;
   if (c->meas_alpha > 1.0) return HPT_EINVAL;
   if (!(c->qr_rank_tol < 1.0)) return HPT_EINVAL;
@@ -437,9 +437,13 @@ int phase_a_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, uint32_t& 
     // G2 = Q1^T Q1 = R2^T R2.  Then X = (Q1 R2^{-1}) (R2 R1) and Q = X W1 R2^{-1}.
     RC(gram<T>(s, n, m, psi, m, s->G1));
     // with tolerance 0 the pivoted factorisation stops at the first pivot
-    // below 1e-13 of the largest and the block goes to Householder instead
+    // below 1e-13 of the largest and the block goes to Householder instead;
+    // with a positive tolerance a failed second pass is retried with the
+    // tolerance raised 100-fold (twice) before Householder is used
     const bool deflate = s->cfg_qr_tol > 0.0;
-    PivCholJob pj{s->G1, n, n, s->R1, n, s->sel, s->info + 1, deflate ? s->cfg_qr_tol : 1e-13};
+    double tol = deflate ? s->cfg_qr_tol : 1e-13;
+    for (int attempt = 0; attempt < (deflate ? 3 : 1) && !P.chol; ++attempt, tol *= 100.0) {
+    PivCholJob pj{s->G1, n, n, s->R1, n, s->sel, s->info + 1, tol};
     PivCholJob* pjd;
     RC(stage(s, &pj, 1, &pjd));
     KR(launch_piv_cholesky(pjd, 1, s->stream));
@@ -493,6 +497,7 @@ int phase_a_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, uint32_t& 
         P.chol = 1;
         P.k = r;
       }
+    }
     }
     if (!P.chol) flags |= HPT_FLAG_QR_FALLBACK;
   }
@@ -1109,7 +1114,7 @@ int hpt_config_default(hpt_config* c) {
   c->qr_mode = HPT_QR_ADAPTIVE;
   c->chol_min_ratio = 2;
   c->chol_min_cols = 16;
-  c->eps_cut = 1e-11;
+  c->eps_cut = -1.0;
   c->eps_pinv = 1e-12;
   c->bp_alpha = 0.5;
   c->bp_tol = 1e-10;
@@ -1241,6 +1246,10 @@ int hpt_create(const hpt_config* cfg, void* arena, uint64_t arena_bytes, void* h
   // column sends the block to Householder), float32 form deflates columns
   // whose remaining pivot is below the float32 resolution of the Gram matrix
   s->cfg_qr_tol = cfg->qr_rank_tol >= 0.0 ? cfg->qr_rank_tol : (s->fp32 ? 1e-12 : 0.0);
+  // eps_cut < 0: 1e-11 (the paper's default) in the float64 form; in the
+  // float32 form singular values near 1e-7 s_0 are rounding noise of the
+  // float32 site tensors, so the cutoff is raised to 1e-7 s_0 there
+  if (s->cfg.eps_cut < 0.0) s->cfg.eps_cut = s->fp32 ? 1e-7 : 1e-11;
   r = s->fp32 ? reset_t<float>(s) : reset_t<double>(s);
   if (r) {
     hpt_destroy(s);

@@ -28,7 +28,7 @@ def test_every_declared_symbol_is_exported(hpt):
 def test_config_defaults(hpt):
     c = hpt.make_config()
     assert (c.Lx, c.Ly, c.chi_max) == (3, 3, 8)
-    assert c.eps_cut == 1e-11 and c.bp_alpha == 0.5 and c.bp_tol == 1e-10
+    assert c.eps_cut == -1.0 and c.bp_alpha == 0.5 and c.bp_tol == 1e-10
     assert c.cx == -1 and c.cy == -1 and c.trap_sweeps == 30
 
 
