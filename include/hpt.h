@@ -184,14 +184,26 @@ int hpt_destroy(hpt_sim* sim);
 const char* hpt_strerror(int code);
 const char* hpt_last_hip_error(void);
 
-/* Process-wide timing of the MFMA GEMM kernel (gemm_kernel): when enabled,
- * every launch is bracketed by HIP events on its stream.  Enabling (again)
- * clears the counters.  hpt_profile_gemm_read waits for the recorded events
- * and fills out4 = {launches, total milliseconds, algorithmic flops
- * (2 M N K per product), algorithmic bytes (operands read once, result
- * written once)}.  For the roofline report of the contractions. */
+/* Process-wide timing of the MFMA contraction kernels: when enabled, every
+ * launch is bracketed by HIP events on its stream.  Enabling (again) clears
+ * the counters.  hpt_profile_read waits for the recorded events and fills
+ * out4 = {launches, total milliseconds, algorithmic flops (2 M N K per
+ * product, half for a symmetric Gram), algorithmic bytes (operands read once,
+ * result written once)} for one kernel kind: HPT_PROF_GEMM (gemm_pipe_kernel:
+ * general tiled GEMM), HPT_PROF_GRAM64 (the same kernel with float64
+ * products and accumulation of float32 data: CholeskyQR Grams),
+ * HPT_PROF_MODE (mode_product_kernel: float32 mode products with the factor
+ * resident in LDS), HPT_PROF_LEGGRAM (leg_gram_kernel: float32 leg Grams of
+ * the gauge BP, with their partial-sum pass), or -1 for all of them.  hpt_profile_gemm_read(out4) is
+ * hpt_profile_read(-1, out4).  For the roofline report of the contractions.
+ * Returns HPT_EINVAL for a null out4 or an unknown kind. */
+#define HPT_PROF_GEMM 0
+#define HPT_PROF_GRAM64 1
+#define HPT_PROF_MODE 2
+#define HPT_PROF_LEGGRAM 3
 int hpt_profile_gemm(int32_t enable);
 int hpt_profile_gemm_read(double* out4);
+int hpt_profile_read(int32_t kind, double* out4);
 
 /* Permute a column-major tensor on the device (Sec. "GPU Tensor Permutation").
  * in/out: device pointers, not overlapping; ndim <= 8; dims of the input;

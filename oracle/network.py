@@ -241,13 +241,13 @@ class OperatorNetwork:
         rs = np.sqrt(sk)
         M1 = U[:, :chi_new].reshape(k1, 4, chi_new) * rs[None, None, :]      # [k1, e1, j]
         M2 = Vt[:chi_new, :].T.reshape(k2, 4, chi_new) * rs[None, None, :]   # [k2, e2, j]
-        cv1 = np.einsum("mk,kej->mje", A["Q"], M1)                           # [m1, j, p]
+        cv1 = np.einsum("mk,kej->mje", A["Q"], M1, optimize=True)                         # [m1, j, p]
         w = gauge_sign_weights(A["m"] * 4).reshape((A["m"], 4), order="F")
-        t = np.einsum("mje,me->j", cv1, w)
+        t = np.einsum("mje,me->j", cv1, w, optimize=True)
         flip = t < 0
         cv1[:, flip, :] *= -1.0
         M2[:, :, flip] *= -1.0
-        cv2 = np.einsum("mk,kej->mje", B["Q"], M2)
+        cv2 = np.einsum("mk,kej->mje", B["Q"], M2, optimize=True)
         for side, cv in ((A, cv1), (B, cv2)):
             T = cv.reshape(tuple(side["env_dims"]) + (chi_new, 4), order="F")
             T = np.transpose(T, np.argsort(side["order"]))              # inverse permute

@@ -53,9 +53,26 @@ struct GemmDesc {
 template <typename T>
 int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s);
 
-// process-wide event timing of gemm_kernel launches
+// process-wide event timing of the contraction launches; kind 0 gemm_pipe_kernel,
+// 1 its float64-accumulated Gram, 2 mode_product_kernel, 3 leg_gram_kernel, -1 all
 int gemm_profile(int enable);
-int gemm_profile_read(double* out4);
+int gemm_profile_read(int kind, double* out4);
+
+// Mode product of the float32 form, dst = src x_axis S with the n x n factor
+// S resident in LDS: dst[a, j, b] = sum_k S[j, k] src[a, k, b] for a < inner,
+// b < outer (column-major).  Returns 1 when done, 0 when the shape is not
+// served (n > 128, or a short leading extent; the caller uses gemm), < 0 on
+// a HIP error.
+int mode_product_f32(const float* S, const float* src, float* dst, int n, int64_t inner, int64_t outer,
+                     hipStream_t s);
+
+// Leg Gram of the float32 form: out[i, j] (n x n, float64) = sum over a < inner,
+// b < outer of psi[a, i, b] cur[a, j, b] (column-major), float32 MFMA products
+// accumulated per workgroup, float64 partials (part, n^2 per workgroup, at
+// most part_cap entries) summed in a fixed order.  Returns 1 when done, 0 when
+// not served (n > 128), < 0 on a HIP error.
+int leg_gram_f32(const float* psi, const float* cur, int n, int64_t inner, int64_t outer, double* out, double* part,
+                 int64_t part_cap, hipStream_t s);
 
 // Tensor permutation (k_permute.hip).
 int permute_generic(const void* in, void* out, int ndim, const int64_t* dims,

@@ -66,6 +66,11 @@ struct BondSlot {
   float* W32[2];
   double* z;
   double* lam;
+  int* svd_state;
+  // float32 form: float64 scratch of the batched CholeskyQR2 steps, per side
+  double* qa[2][8];
+  int* qsel[2];
+  int* qinfo[2];    // [0] Cholesky info, [1] pivoted-Cholesky rank
 };
 
 }  // namespace hpt

@@ -8,6 +8,7 @@
 // Sec. "Correlation Function via Belief Propagation", implementation
 // pipeline figure (order of one time step), Table "Runtime diagnostic
 // measures".
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -154,7 +155,21 @@ uint64_t slot_layout(int C, bool fp32, char* base, BondSlot* sl) {
   void* Vc = take(n4 * (uint64_t)C * 8);
   void* z = take(n4 * 4 * 8);
   void* lam = take((uint64_t)C * 8);
+  void* sst = take(64);
+  for (int i = 0; i < 2; ++i) {
+    for (int a = 0; a < 8; ++a) {
+      void* q = fp32 ? take(n4 * n4 * 8) : nullptr;
+      if (sl) sl->qa[i][a] = (double*)q;
+    }
+    void* qs = fp32 ? take(n4 * 4) : nullptr;
+    void* qi = fp32 ? take(64) : nullptr;
+    if (sl) {
+      sl->qsel[i] = (int*)qs;
+      sl->qinfo[i] = (int*)qi;
+    }
+  }
   if (sl) {
+    sl->svd_state = (int*)sst;
     sl->tau = (double*)tau;
     sl->G = (double*)G;
     sl->V = (double*)V;
@@ -263,6 +278,12 @@ int mode_product(hpt_sim* s, const T* src, T* dst, const int64_t* dims, int nd, 
   for (int i = 0; i < axis; ++i) inner *= dims[i];
   for (int i = axis + 1; i < nd; ++i) outer *= dims[i];
   const int n = (int)dims[axis];
+  if (sizeof(T) == 4) {
+    // float32 form: the factor is resident in LDS
+    const int r = mode_product_f32((const float*)S, (const float*)src, (float*)dst, n, inner, outer, s->stream);
+    KR(r < 0 ? r : 0);
+    if (r == 1) return 0;
+  }
   GemmDesc<T> d{};
   if (inner == 1) {
     d.M = n; d.N = (int)outer; d.K = n; d.R = 1; d.Z = 1;
@@ -287,6 +308,12 @@ int leg_gram(hpt_sim* s, const T* psi, const T* cur, const int64_t* dims, int nd
   for (int i = 0; i < axis; ++i) inner *= dims[i];
   for (int i = axis + 1; i < nd; ++i) outer *= dims[i];
   const int n = (int)dims[axis];
+  if (sizeof(T) == 4) {
+    const int r = leg_gram_f32((const float*)psi, (const float*)cur, n, inner, outer, out, s->part, s->cv.part_cap,
+                               s->stream);
+    KR(r < 0 ? r : 0);
+    if (r == 1) return 0;
+  }
   GemmDesc<T> d{};
   if (inner == 1) {
     d.M = n; d.N = n; d.K = (int)outer; d.R = 1; d.Z = 1;
@@ -377,7 +404,12 @@ struct SitePlan {
   int64_t m, n;
   int chol;
   int k;
+  int deferred;     // float32 form: Gram taken, CholeskyQR2 algebra pending
+  int was_deferred;
 };
+
+template <typename T>
+int phase_a_finish(hpt_sim* s, int i, BondSlot& sl, SitePlan& P);
 
 template <typename T>
 const T* env_S(BondSlot& sl, int i, int e, bool inv);
@@ -431,6 +463,16 @@ int phase_a_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, uint32_t& 
   P.chol = 0;
   bool use_chol = s->cfg.qr_mode == HPT_QR_ADAPTIVE && m >= (int64_t)s->cfg.chol_min_ratio * n &&
                   n >= s->cfg.chol_min_cols;
+  P.deferred = 0;
+  P.was_deferred = 0;
+  if (use_chol && s->fp32) {
+    // float32 form: only the Gram here; the float64 algebra of every block of
+    // the colour runs batched afterwards
+    RC(gram<T>(s, n, m, psi, m, sl.qa[i][0]));
+    P.deferred = 1;
+    P.was_deferred = 1;
+    return 0;
+  }
   if (use_chol) {
     // rank-revealing CholeskyQR2: G1 = X^T X; pivoted Cholesky R1 (rank r,
     // exact structural zeros deflated); Q1 = X W1 with W1 = E_sel R1sel^{-1};
@@ -493,7 +535,7 @@ int phase_a_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, uint32_t& 
         gj[1] = SmallGemmJob{n, r, r, nullptr, nullptr, nullptr, s->W1, n, 0, s->Ri2, r, 0, sl.Rinv[i], ldR, 1.0, 0.0, nullptr};
         SmallGemmJob* gjd;
         RC(stage(s, gj, 2, &gjd));
-        KR(launch_small_gemm(gjd, 2, s->stream));
+        KR(launch_small_gemm(gjd, gj, 2, s->stream));
         P.chol = 1;
         P.k = r;
       }
@@ -501,9 +543,20 @@ int phase_a_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, uint32_t& 
     }
     if (!P.chol) flags |= HPT_FLAG_QR_FALLBACK;
   }
+  (void)bi;
+  return phase_a_finish<T>(s, i, sl, P);
+}
+
+// Householder QR of X when the Cholesky route was not taken or failed, then
+// the sign projections of S_0 (X_0 or Q_0)
+template <typename T>
+int phase_a_finish(hpt_sim* s, int i, BondSlot& sl, SitePlan& P) {
+  T* psi = psi_of<T>(s, P.v);
+  const int n = (int)P.n;
+  const int64_t m = P.m;
   if (!P.chol) {
     if (std::min<int64_t>(m, n) > 1024) return HPT_EINVAL;
-    QrJob<T> qj{psi, m, (int)m, n, sl.R[i], ldR, s->R1 /* tau scratch */, 1, nullptr};
+    QrJob<T> qj{psi, m, (int)m, n, sl.R[i], 4 * s->chi_max, s->R1 /* tau scratch */, 1, nullptr, 0};
     QrJob<T>* qjd;
     RC(stage(s, &qj, 1, &qjd));
     KR(launch_householder<T>(qjd, 1, s->stream));
@@ -513,7 +566,134 @@ int phase_a_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, uint32_t& 
     const int ncols = P.chol ? n : P.k;
     KR(launch_sign_projection<T>(psi, m, m, ncols, sl.z, s->part, s->cv.part_cap, s->stream));
   }
-  (void)bi;
+  return 0;
+}
+
+// float32 form: the float64 algebra of the rank-revealing CholeskyQR2 of every
+// deferred block of the colour, batched one workgroup per block.  With G1 =
+// X^T X already formed: pivoted Cholesky R1 (rank r); W1 = E_sel R1sel^{-1};
+// the second pass takes its Gram algebraically, G2 = W1^T G1 W1 = R2^T R2, in
+// float64 rather than from an explicit float32 Q1 = X W1 (whose rounding would
+// only add noise: Q is never formed, X W1 R2^{-1} is the basis used).  Then
+// R = R2 R1 and Rinv = W1 R2^{-1}.  A block whose second Cholesky fails is
+// retried with the deflation tolerance raised 100-fold (twice), then goes to
+// Householder.
+template <typename T>
+int phase_a_batched(hpt_sim* s, std::vector<SitePlan>& plans, uint32_t& flags) {
+  std::vector<int> pend;
+  for (int p = 0; p < (int)plans.size(); ++p)
+    if (plans[p].deferred) pend.push_back(p);
+  const int ldR = 4 * s->chi_max;
+  const bool deflate = s->cfg_qr_tol > 0.0;
+  double tol = deflate ? s->cfg_qr_tol : 1e-13;
+  for (int attempt = 0; attempt < (deflate ? 3 : 1) && !pend.empty(); ++attempt, tol *= 100.0) {
+    const int np = (int)pend.size();
+    std::vector<PivCholJob> pj;
+    for (int p : pend) {
+      BondSlot& sl = s->slots[p / 2];
+      const int i = p % 2, n = (int)plans[p].n;
+      pj.push_back(PivCholJob{sl.qa[i][0], n, n, sl.qa[i][1], n, sl.qsel[i], sl.qinfo[i] + 1, tol});
+    }
+    PivCholJob* pjd;
+    RC(stage(s, pj.data(), np, &pjd));
+    KR(launch_piv_cholesky(pjd, np, s->stream));
+    for (int a = 0; a < np; ++a)
+      HPT_HIP(hipMemcpyAsync(s->hscratch + 4 * a, s->slots[pend[a] / 2].qinfo[pend[a] % 2] + 1, sizeof(int),
+                             hipMemcpyDeviceToHost, s->stream));
+    RC(sync_stream(s));
+    std::vector<int> rank(np), go;
+    std::memcpy(rank.data(), s->hscratch, sizeof(int) * np);
+    for (int a = 0; a < np; ++a) {
+      const int r = rank[a], n = (int)plans[pend[a]].n;
+      if (r >= 1 && r <= n && (deflate || r == n)) go.push_back(a);
+    }
+    std::vector<int> next;
+    for (int a = 0; a < np; ++a)
+      if (std::find(go.begin(), go.end(), a) == go.end()) next.push_back(pend[a]);
+    if (!go.empty()) {
+      const int ng = (int)go.size();
+      std::vector<SelJob> gat, sca;
+      std::vector<TriInvJob> ti;
+      std::vector<SmallGemmJob> g1, g2;
+      std::vector<CholJob> cj;
+      for (int a : go) {
+        const int p = pend[a], i = p % 2, r = rank[a], n = (int)plans[p].n;
+        BondSlot& sl = s->slots[p / 2];
+        double** q = sl.qa[i];
+        gat.push_back(SelJob{0, q[1], n, q[2], r, sl.qsel[i], r, n});
+        ti.push_back(TriInvJob{q[2], r, r, q[3], r, nullptr, 0});
+        sca.push_back(SelJob{1, q[3], r, q[4], n, sl.qsel[i], r, n});
+        SmallGemmJob a1{}, a2{};
+        a1 = SmallGemmJob{n, r, n, nullptr, nullptr, nullptr, q[0], n, 0, q[4], n, 0, q[5], n, 1.0, 0.0, nullptr, 0};
+        a2 = SmallGemmJob{r, r, n, nullptr, nullptr, nullptr, q[4], n, 1, q[5], n, 0, q[6], r, 1.0, 0.0, nullptr, 0};
+        g1.push_back(a1);
+        g2.push_back(a2);
+        cj.push_back(CholJob{q[6], r, r, q[6], r, sl.qinfo[i], nullptr, 0, nullptr});
+      }
+      SelJob* sd;
+      RC(stage(s, gat.data(), ng, &sd));
+      KR(launch_sel(sd, ng, s->stream));
+      TriInvJob* td;
+      RC(stage(s, ti.data(), ng, &td));
+      KR(launch_tri_inverse(td, ng, s->stream));
+      RC(stage(s, sca.data(), ng, &sd));
+      KR(launch_sel(sd, ng, s->stream));
+      SmallGemmJob* gd;
+      RC(stage(s, g1.data(), ng, &gd));
+      KR(launch_small_gemm(gd, g1.data(), ng, s->stream));
+      RC(stage(s, g2.data(), ng, &gd));
+      KR(launch_small_gemm(gd, g2.data(), ng, s->stream));
+      CholJob* cd;
+      RC(stage(s, cj.data(), ng, &cd));
+      KR(launch_cholesky(cd, ng, 1e-13, s->stream));
+      for (int a = 0; a < ng; ++a) {
+        const int p = pend[go[a]];
+        HPT_HIP(hipMemcpyAsync(s->hscratch + 4 * a, s->slots[p / 2].qinfo[p % 2], sizeof(int),
+                               hipMemcpyDeviceToHost, s->stream));
+      }
+      RC(sync_stream(s));
+      std::vector<int> info(ng);
+      std::memcpy(info.data(), s->hscratch, sizeof(int) * ng);
+      std::vector<TriInvJob> t2;
+      std::vector<SmallGemmJob> fin;
+      for (int a = 0; a < ng; ++a) {
+        const int p = pend[go[a]], i = p % 2, r = rank[go[a]], n = (int)plans[p].n;
+        if (info[a] != 0) {
+          next.push_back(p);
+          continue;
+        }
+        BondSlot& sl = s->slots[p / 2];
+        double** q = sl.qa[i];
+        t2.push_back(TriInvJob{q[6], r, r, q[7], r, nullptr, 0});
+        // R = R2 R1 (r x n), Rinv = W1 R2^{-1} (n x r), both ld 4 chi_max
+        fin.push_back(SmallGemmJob{r, n, r, nullptr, nullptr, nullptr, q[6], r, 0, q[1], n, 0, sl.R[i], ldR, 1.0, 0.0, nullptr, 0});
+        fin.push_back(SmallGemmJob{n, r, r, nullptr, nullptr, nullptr, q[4], n, 0, q[7], r, 0, sl.Rinv[i], ldR, 1.0, 0.0, nullptr, 0});
+        plans[p].chol = 1;
+        plans[p].k = r;
+        plans[p].deferred = 0;
+        if (r < n) flags |= HPT_FLAG_QR_RANK_DEFICIENT;
+      }
+      if (!t2.empty()) {
+        RC(stage(s, t2.data(), (int)t2.size(), &td));
+        KR(launch_tri_inverse(td, (int)t2.size(), s->stream));
+        RC(stage(s, fin.data(), (int)fin.size(), &gd));
+        KR(launch_small_gemm(gd, fin.data(), (int)fin.size(), s->stream));
+      }
+    }
+    pend.swap(next);
+  }
+  for (int p : pend) {
+    plans[p].deferred = 0;
+    plans[p].chol = 0;
+    flags |= HPT_FLAG_QR_FALLBACK;
+  }
+  // Householder for the blocks that failed, sign projections of every
+  // deferred block's S_0
+  for (int p = 0; p < (int)plans.size(); ++p) {
+    SitePlan& P = plans[p];
+    if (!P.was_deferred) continue;
+    RC(phase_a_finish<T>(s, p % 2, s->slots[p / 2], P));
+  }
   return 0;
 }
 
@@ -608,6 +788,7 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
   // phase A: absorb, permute, QR
   for (int q = 0; q < nb; ++q)
     for (int i = 0; i < 2; ++i) RC(phase_a_site<T>(s, cbonds[q], i, s->slots[q], plans[2 * q + i], flags));
+  if (s->fp32) RC(phase_a_batched<T>(s, plans, flags));
   // phase B: R-core of every bond of the colour
   std::vector<BondCore> cores(nb);
   const int C = s->chi_max, ldR = 4 * C;
@@ -630,6 +811,9 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
       bc.Mp[i] = sl.Mp[i];
       bc.W[i] = sl.W[i];
       bc.msg[i] = gmsg_slot(s, b, i);
+      // float32 form: CholeskyQR2 of B_i when it is tall (4 k_i >= 4 chi_cut)
+      bc.bqr[i] = (s->fp32 && P.k >= bc.chi_cut) ? 0 : 1;
+      for (int a = 0; a < 8; ++a) bc.qs[i][a] = sl.qa[i][a];
     }
     bc.chi_max = C;
     bc.eps_cut = s->cfg.eps_cut;
@@ -652,13 +836,66 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
   std::memcpy(s->hscratch, cores.data(), sizeof(BondCore) * nb);
   HPT_HIP(hipMemcpyAsync(cd, s->hscratch, sizeof(BondCore) * nb, hipMemcpyHostToDevice, s->stream));
   KR(launch_rcore_build_B(cd, nb, s->gf, s->stream));
+  bool any_bchol = false;
+  for (int q = 0; q < nb; ++q) any_bchol = any_bchol || cores[q].bqr[0] == 0 || cores[q].bqr[1] == 0;
+  if (any_bchol) {
+    // CholeskyQR2 of the tall B_i: G_B = B^T B assembled from R^T R (the gate
+    // factors act on the Pauli pair only), R1 = chol(G_B), second pass taken
+    // algebraically, G2 = R1^{-T} G_B R1^{-1} = R2^T R2; T_i = R2 R1 and
+    // T_i^{-1} = R1^{-1} R2^{-1} (Q~_i = B_i T_i^{-1} is never formed).  A
+    // failed Cholesky sets bqr[i] = 1 and B_i goes to Householder below.
+    std::vector<SmallGemmJob> rtr, g1, g2, fin;
+    std::vector<CholJob> c1, c2;
+    std::vector<TriInvJob> t1, t2;
+    for (int q = 0; q < nb; ++q)
+      for (int i = 0; i < 2; ++i) {
+        const BondCore& bc = cores[q];
+        if (bc.bqr[i] != 0) continue;
+        const int n = 4 * bc.chi_cut, k = bc.k[i];
+        const int* gq = &cd[q].bqr[i];
+        int* fq = &cd[q].bqr[i];
+        double* const* x = bc.qs[i];
+        int* info = s->slots[q].qinfo[i];
+        rtr.push_back(SmallGemmJob{n, n, k, nullptr, nullptr, nullptr, bc.R[i], ldR, 1, bc.R[i], ldR, 0, x[5], n, 1.0, 0.0, gq, 1});
+        c1.push_back(CholJob{x[0], n, n, x[1], n, info, gq, 1, fq});
+        t1.push_back(TriInvJob{x[1], n, n, x[3], n, gq, 1});
+        g1.push_back(SmallGemmJob{n, n, n, nullptr, nullptr, nullptr, x[0], n, 0, x[3], n, 0, x[4], n, 1.0, 0.0, gq, 1});
+        g2.push_back(SmallGemmJob{n, n, n, nullptr, nullptr, nullptr, x[3], n, 1, x[4], n, 0, x[6], n, 1.0, 0.0, gq, 1});
+        c2.push_back(CholJob{x[6], n, n, x[6], n, info, gq, 1, fq});
+        t2.push_back(TriInvJob{x[6], n, n, x[7], n, gq, 1});
+        fin.push_back(SmallGemmJob{n, n, n, nullptr, nullptr, nullptr, x[6], n, 0, x[1], n, 0, bc.Tm[i], ldR, 1.0, 0.0, gq, 1});
+        fin.push_back(SmallGemmJob{n, n, n, nullptr, nullptr, nullptr, x[3], n, 0, x[7], n, 0, x[2], n, 1.0, 0.0, gq, 1});
+      }
+    const int nj = (int)c1.size();
+    SmallGemmJob* gd;
+    CholJob* chd;
+    TriInvJob* tid;
+    RC(stage(s, rtr.data(), nj, &gd));
+    KR(launch_small_gemm(gd, rtr.data(), nj, s->stream));
+    KR(launch_rcore_kron_gram(cd, nb, s->gf, s->stream));
+    RC(stage(s, c1.data(), nj, &chd));
+    KR(launch_cholesky(chd, nj, 1e-10, s->stream));
+    RC(stage(s, t1.data(), nj, &tid));
+    KR(launch_tri_inverse(tid, nj, s->stream));
+    RC(stage(s, g1.data(), nj, &gd));
+    KR(launch_small_gemm(gd, g1.data(), nj, s->stream));
+    RC(stage(s, g2.data(), nj, &gd));
+    KR(launch_small_gemm(gd, g2.data(), nj, s->stream));
+    RC(stage(s, c2.data(), nj, &chd));
+    KR(launch_cholesky(chd, nj, 1e-10, s->stream));
+    RC(stage(s, t2.data(), nj, &tid));
+    KR(launch_tri_inverse(tid, nj, s->stream));
+    RC(stage(s, fin.data(), 2 * nj, &gd));
+    KR(launch_small_gemm(gd, fin.data(), 2 * nj, s->stream));
+  }
   {
+    // Householder (explicit Q~_i into B_i) where bqr[i] != 0
     std::vector<QrJob<double>> qj;
     for (int q = 0; q < nb; ++q)
       for (int i = 0; i < 2; ++i) {
         const BondCore& bc = cores[q];
         qj.push_back(QrJob<double>{bc.B[i], 4 * bc.k[i], 4 * bc.k[i], 4 * bc.chi_cut, bc.Tm[i], ldR,
-                                   s->slots[q].tau + i * 4 * C, 1, nullptr});
+                                   s->slots[q].tau + i * 4 * C, 1, &cd[q].bqr[i], 0});
       }
     QrJob<double>* qd;
     RC(stage(s, qj.data(), (int)qj.size(), &qd));
@@ -677,29 +914,48 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
       else
         j = SmallGemmJob{q1, q0, K, nullptr, nullptr, nullptr, bc.Tm[1], ldR, 0, bc.Tm[0], ldR, 1, bc.G, ldR, 1.0, 0.0, nullptr};
       gj.push_back(j);
-      sj.push_back(SvdJob{bc.G, ldR, std::max(q0, q1), std::min(q0, q1), bc.V, ldR, bc.s, bc.perm, nullptr});
+      sj.push_back(SvdJob{bc.G, ldR, std::max(q0, q1), std::min(q0, q1), bc.V, ldR, bc.s, bc.perm, nullptr,
+                          s->slots[q].svd_state});
     }
     SmallGemmJob* gd;
     RC(stage(s, gj.data(), nb, &gd));
-    KR(launch_small_gemm(gd, nb, s->stream));
+    KR(launch_small_gemm(gd, gj.data(), nb, s->stream));
     SvdJob* sd;
     RC(stage(s, sj.data(), nb, &sd));
-    KR(launch_jacobi_svd(sd, nb, s->stream));
+    // block Jacobi (many workgroups per SVD) when any core is wider than 64
+    int nmax = 0;
+    for (auto& j : sj) nmax = std::max(nmax, j.n);
+    if (nmax > 64)
+      KR(launch_block_jacobi_svd(sd, sj.data(), nb, s->stream));
+    else
+      KR(launch_jacobi_svd(sd, nb, s->stream));
   }
   KR(launch_rcore_select(cd, nb, s->stream));
   {
-    std::vector<SmallGemmJob> gj;
+    // Mf_i = Q~_i (U | V): Householder blocks hold Q~_i in B_i; CholeskyQR2
+    // blocks use B_i (T_i^{-1} (U | V))
+    std::vector<SmallGemmJob> tu, gj;
     for (int q = 0; q < nb; ++q) {
       const BondCore& bc = cores[q];
       for (int i = 0; i < 2; ++i) {
-        SmallGemmJob j{4 * bc.k[i], 0, bc.q[i], nullptr, &cd[q].chi_new, nullptr, bc.B[i], 4 * bc.k[i], 0,
-                       i == 0 ? bc.Uc : bc.Vc, ldR, 0, bc.Mf[i], 4 * bc.k[i], 1.0, 0.0, nullptr};
-        gj.push_back(j);
+        const double* UV = i == 0 ? bc.Uc : bc.Vc;
+        const int n = 4 * bc.chi_cut, m4 = 4 * bc.k[i];
+        gj.push_back(SmallGemmJob{m4, C, bc.q[i], nullptr, &cd[q].chi_new, nullptr, bc.B[i], m4, 0, UV, ldR, 0,
+                                  bc.Mf[i], m4, 1.0, 0.0, &cd[q].bqr[i], 0});
+        if (bc.bqr[i] != 0) continue;
+        tu.push_back(SmallGemmJob{n, C, n, nullptr, &cd[q].chi_new, nullptr, bc.qs[i][2], n, 0, UV, ldR, 0,
+                                  bc.qs[i][5], n, 1.0, 0.0, &cd[q].bqr[i], 1});
+        gj.push_back(SmallGemmJob{m4, C, n, nullptr, &cd[q].chi_new, nullptr, bc.B[i], m4, 0, bc.qs[i][5], n, 0,
+                                  bc.Mf[i], m4, 1.0, 0.0, &cd[q].bqr[i], 1});
       }
     }
     SmallGemmJob* gd;
+    if (!tu.empty()) {
+      RC(stage(s, tu.data(), (int)tu.size(), &gd));
+      KR(launch_small_gemm(gd, tu.data(), (int)tu.size(), s->stream));
+    }
     RC(stage(s, gj.data(), (int)gj.size(), &gd));
-    KR(launch_small_gemm(gd, (int)gj.size(), s->stream));
+    KR(launch_small_gemm(gd, gj.data(), (int)gj.size(), s->stream));
   }
   KR(launch_rcore_rearrange(cd, nb, s->stream));
   {
@@ -709,7 +965,7 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
       for (int i = 0; i < 2; ++i) {
         if (!bc.chol[i]) continue;
         const int n = 4 * bc.chi_cut;
-        SmallGemmJob j{n, 0, bc.k[i], nullptr, &cd[q].n4, nullptr, bc.Rinv[i], ldR, 0, bc.Mp[i], bc.k[i], 0,
+        SmallGemmJob j{n, 4 * C, bc.k[i], nullptr, &cd[q].n4, nullptr, bc.Rinv[i], ldR, 0, bc.Mp[i], bc.k[i], 0,
                        bc.W[i], n, 1.0, 0.0, nullptr};
         gj.push_back(j);
       }
@@ -717,7 +973,7 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
     if (!gj.empty()) {
       SmallGemmJob* gd;
       RC(stage(s, gj.data(), (int)gj.size(), &gd));
-      KR(launch_small_gemm(gd, (int)gj.size(), s->stream));
+      KR(launch_small_gemm(gd, gj.data(), (int)gj.size(), s->stream));
     }
   }
   KR(launch_rcore_signs(cd, nb, s->stream));
@@ -1420,9 +1676,11 @@ int hpt_profile_gemm(int32_t enable) {
   return r == 0 ? HPT_OK : HPT_EHIP;
 }
 
-int hpt_profile_gemm_read(double* out4) {
-  if (!out4) return HPT_EINVAL;
-  const int r = gemm_profile_read(out4);
+int hpt_profile_gemm_read(double* out4) { return hpt_profile_read(-1, out4); }
+
+int hpt_profile_read(int32_t kind, double* out4) {
+  if (!out4 || kind < -1 || kind > 3) return HPT_EINVAL;
+  const int r = gemm_profile_read(kind, out4);
   return r == 0 ? HPT_OK : HPT_EHIP;
 }
 

@@ -15,9 +15,11 @@
 
 namespace hpt {
 
+#define RC_PROF(x) do { const int _r = (x); if (_r) return _r; } while (0)
+
 namespace {
 
-constexpr int TM = 64, TN = 64, TK = 16, PAD = 2;
+constexpr int TK = 16;
 
 __device__ inline d4 mfma_op(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -73,130 +75,23 @@ __device__ inline void put(const GemmDesc<T>& d, int z, int gi, int gj, double v
   }
 }
 
+// Tile (2 WT) x (2 WT): four waves in a 2 x 2 grid, each owning WT x WT as
+// (WT/16)^2 blocks of the 16x16x4 MFMA.  Depth-16 chunks of op(A) and op(B)
+// are double-buffered in LDS; the next chunk is fetched into registers while
+// the current one feeds the MFMAs, so global latency overlaps the math.
 // T: storage type of A and B; TC: MFMA type (T, or double for float inputs
-// whose products must be accumulated in float64)
-template <typename T, typename TC>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmDesc<T> d, int tiles_m, int tiles_n,
-                                                   int splits, int64_t chunks_per_r,
-                                                   double* part) {
+// whose products must be accumulated in float64).
+template <typename T, typename TC, int WT>
+__global__ __launch_bounds__(256) void gemm_pipe_kernel(GemmDesc<T> d, int tiles_m, int tiles_n,
+                                                        int splits, int64_t chunks_per_r,
+                                                        double* part) {
   typedef typename Acc<TC>::type acc_t;
-  __shared__ TC As[TK][TM + PAD];
-  __shared__ TC Bs[TK][TN + PAD];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-
-  int z, tm, tn;
-  tile_of(blockIdx.x, tiles_m, tiles_n, d.sym, z, tm, tn);
-  const int split = blockIdx.y;
-
-  const int64_t total = (int64_t)d.R * chunks_per_r;
-  const int64_t per = (total + splits - 1) / splits;
-  const int64_t c_begin = (int64_t)split * per;
-  const int64_t c_end = c_begin + per < total ? c_begin + per : total;
-
-  acc_t acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
-      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
-
-  const T* Az = d.A + (int64_t)z * d.sAz;
-  const T* Bz = d.B + (int64_t)z * d.sBz;
-  const int row0 = tm * TM, col0 = tn * TN;
-
-  for (int64_t c = c_begin; c < c_end; ++c) {
-    const int64_t r = c / chunks_per_r;
-    const int k0 = (int)((c % chunks_per_r) * TK);
-    const T* Ar = Az + r * d.sAr;
-    const T* Br = Bz + r * d.sBr;
-    // stage op(A) tile (TM x TK) as As[k][i]
-    if (!d.tA) {
-      const int i = tid & 63;
-      const int gi = row0 + i;
-      for (int q = 0; q < 4; ++q) {
-        const int k = (tid >> 6) + 4 * q;
-        const int gk = k0 + k;
-        TC v = 0;
-        if (gi < d.M && gk < d.K) v = (TC)Ar[gi + (int64_t)gk * d.lda];
-        As[k][i] = v;
-      }
-    } else {
-      const int k = tid & 15;
-      const int gk = k0 + k;
-      for (int q = 0; q < 4; ++q) {
-        const int i = (tid >> 4) + 16 * q;
-        const int gi = row0 + i;
-        TC v = 0;
-        if (gi < d.M && gk < d.K) v = (TC)Ar[gk + (int64_t)gi * d.lda];
-        As[k][i] = v;
-      }
-    }
-    // stage op(B) tile (TK x TN) as Bs[k][j]
-    if (!d.tB) {
-      const int k = tid & 15;
-      const int gk = k0 + k;
-      for (int q = 0; q < 4; ++q) {
-        const int j = (tid >> 4) + 16 * q;
-        const int gj = col0 + j;
-        TC v = 0;
-        if (gj < d.N && gk < d.K) v = (TC)Br[gk + (int64_t)gj * d.ldb];
-        Bs[k][j] = v;
-      }
-    } else {
-      const int j = tid & 63;
-      const int gj = col0 + j;
-      for (int q = 0; q < 4; ++q) {
-        const int k = (tid >> 6) + 4 * q;
-        const int gk = k0 + k;
-        TC v = 0;
-        if (gj < d.N && gk < d.K) v = (TC)Br[gj + (int64_t)gk * d.ldb];
-        Bs[k][j] = v;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK / 4; ++kk) {
-      const int kr = kk * 4 + (lane >> 4);
-      TC a0 = As[kr][wr * 32 + (lane & 15)];
-      TC a1 = As[kr][wr * 32 + 16 + (lane & 15)];
-      TC b0 = Bs[kr][wc * 32 + (lane & 15)];
-      TC b1 = Bs[kr][wc * 32 + 16 + (lane & 15)];
-      // operands swapped (B fragment first): the MFMA then produces C^T
-      // blocks whose lane index runs along C's contiguous row axis
-      acc[0][0] = mfma_op(b0, a0, acc[0][0]);
-      acc[0][1] = mfma_op(b1, a0, acc[0][1]);
-      acc[1][0] = mfma_op(b0, a1, acc[1][0]);
-      acc[1][1] = mfma_op(b1, a1, acc[1][1]);
-    }
-    __syncthreads();
-  }
-
-  // write out: block (bi, bj), register e -> row lane%16 and column
-  // 4*(lane/16)+e for the f32 MFMA, lane/16 + 4*e for the f64 MFMA
-  for (int bi = 0; bi < 2; ++bi)
-    for (int bj = 0; bj < 2; ++bj)
-      for (int e = 0; e < 4; ++e) {
-        const int cloc = sizeof(TC) == 8 ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e;
-        const int gi = row0 + wr * 32 + bi * 16 + (lane & 15);
-        const int gj = col0 + wc * 32 + bj * 16 + cloc;
-        if (gi >= d.M || gj >= d.N) continue;
-        put<T>(d, z, gi, gj, (double)acc[bi][bj][e], splits, split, part);
-      }
-}
-
-// 128 x 128 tile, 4 waves of 64 x 64 (4 x 4 MFMA blocks each), depth-16
-// chunks double-buffered in LDS with the next chunk prefetched into registers
-// while the current one feeds the MFMAs.
-constexpr int BT = 128, BPAD = 4;
-template <typename T>
-__global__ __launch_bounds__(256) void gemm_big_kernel(GemmDesc<T> d, int tiles_m, int tiles_n,
-                                                       int splits, int64_t chunks_per_r,
-                                                       double* part) {
-  typedef typename Acc<T>::type acc_t;
-  __shared__ T As[2][TK][BT + BPAD];
-  __shared__ T Bs[2][TK][BT + BPAD];
+  constexpr int BT = 2 * WT;           // tile side
+  constexpr int NB = WT / 16;          // MFMA blocks per wave side
+  constexpr int L = BT * TK / 256;     // elements per thread per operand
+  constexpr int LP = 4;                // LDS row padding
+  __shared__ TC As[2][TK][BT + LP];
+  __shared__ TC Bs[2][TK][BT + LP];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -212,54 +107,44 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(GemmDesc<T> d, int tiles_
   const T* Bz = d.B + (int64_t)z * d.sBz;
   const int row0 = tm * BT, col0 = tn * BT;
 
-  acc_t acc[4][4];
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j)
+  acc_t acc[NB][NB];
+  for (int i = 0; i < NB; ++i)
+    for (int j = 0; j < NB; ++j)
       for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
 
-  T ra[8], rb[8];
+  // thread -> (row-or-col, k) coordinates of its L elements, per operand layout
+  // contiguous-along-tile layout: x = tid % BT, k = tid / BT + (256 / BT) q
+  // contiguous-along-k layout:    k = tid % 16, x = tid / 16 + 16 q
+  TC ra[L], rb[L];
   auto load = [&](int64_t c) {
     const int64_t r = c / chunks_per_r;
     const int k0 = (int)((c % chunks_per_r) * TK);
     const T* Ar = Az + r * d.sAr;
     const T* Br = Bz + r * d.sBr;
-    if (!d.tA) {
-      const int i = tid & 127, gi = row0 + i;
-      for (int q = 0; q < 8; ++q) {
-        const int gk = k0 + (tid >> 7) + 2 * q;
-        ra[q] = (gi < d.M && gk < d.K) ? Ar[gi + (int64_t)gk * d.lda] : (T)0;
-      }
-    } else {
-      const int gk = k0 + (tid & 15);
-      for (int q = 0; q < 8; ++q) {
-        const int gi = row0 + (tid >> 4) + 16 * q;
-        ra[q] = (gi < d.M && gk < d.K) ? Ar[gk + (int64_t)gi * d.lda] : (T)0;
-      }
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      int i, k;
+      if (!d.tA) { i = tid % BT; k = tid / BT + (256 / BT) * q; }
+      else { k = tid & 15; i = (tid >> 4) + 16 * q; }
+      const int gi = row0 + i, gk = k0 + k;
+      ra[q] = (gi < d.M && gk < d.K) ? (TC)(d.tA ? Ar[gk + (int64_t)gi * d.lda] : Ar[gi + (int64_t)gk * d.lda]) : (TC)0;
     }
-    if (!d.tB) {
-      const int gk = k0 + (tid & 15);
-      for (int q = 0; q < 8; ++q) {
-        const int gj = col0 + (tid >> 4) + 16 * q;
-        rb[q] = (gj < d.N && gk < d.K) ? Br[gk + (int64_t)gj * d.ldb] : (T)0;
-      }
-    } else {
-      const int j = tid & 127, gj = col0 + j;
-      for (int q = 0; q < 8; ++q) {
-        const int gk = k0 + (tid >> 7) + 2 * q;
-        rb[q] = (gj < d.N && gk < d.K) ? Br[gj + (int64_t)gk * d.ldb] : (T)0;
-      }
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      int j, k;
+      if (d.tB) { j = tid % BT; k = tid / BT + (256 / BT) * q; }
+      else { k = tid & 15; j = (tid >> 4) + 16 * q; }
+      const int gj = col0 + j, gk = k0 + k;
+      rb[q] = (gj < d.N && gk < d.K) ? (TC)(d.tB ? Br[gj + (int64_t)gk * d.ldb] : Br[gk + (int64_t)gj * d.ldb]) : (TC)0;
     }
   };
   auto store = [&](int buf) {
-    if (!d.tA) {
-      for (int q = 0; q < 8; ++q) As[buf][(tid >> 7) + 2 * q][tid & 127] = ra[q];
-    } else {
-      for (int q = 0; q < 8; ++q) As[buf][tid & 15][(tid >> 4) + 16 * q] = ra[q];
-    }
-    if (!d.tB) {
-      for (int q = 0; q < 8; ++q) Bs[buf][tid & 15][(tid >> 4) + 16 * q] = rb[q];
-    } else {
-      for (int q = 0; q < 8; ++q) Bs[buf][(tid >> 7) + 2 * q][tid & 127] = rb[q];
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      if (!d.tA) As[buf][tid / BT + (256 / BT) * q][tid % BT] = ra[q];
+      else As[buf][tid & 15][(tid >> 4) + 16 * q] = ra[q];
+      if (d.tB) Bs[buf][tid / BT + (256 / BT) * q][tid % BT] = rb[q];
+      else Bs[buf][tid & 15][(tid >> 4) + 16 * q] = rb[q];
     }
   };
 
@@ -274,11 +159,17 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(GemmDesc<T> d, int tiles_
 #pragma unroll
       for (int kk = 0; kk < TK / 4; ++kk) {
         const int kr = kk * 4 + (lane >> 4);
-        T a[4], b[4];
-        for (int i = 0; i < 4; ++i) a[i] = As[buf][kr][wr * 64 + i * 16 + (lane & 15)];
-        for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kr][wc * 64 + j * 16 + (lane & 15)];
-        for (int i = 0; i < 4; ++i)
-          for (int j = 0; j < 4; ++j) acc[i][j] = mfma_op(b[j], a[i], acc[i][j]);
+        TC a[NB], b[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) a[i] = As[buf][kr][wr * WT + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) b[j] = Bs[buf][kr][wc * WT + j * 16 + (lane & 15)];
+        // operands swapped (B fragment first): the MFMA yields C^T blocks whose
+        // lane index runs along C's contiguous row axis
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) acc[i][j] = mfma_op(b[j], a[i], acc[i][j]);
       }
       if (more) store(buf ^ 1);
       __syncthreads();
@@ -286,41 +177,292 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(GemmDesc<T> d, int tiles_
     }
   }
 
-  for (int bi = 0; bi < 4; ++bi)
-    for (int bj = 0; bj < 4; ++bj)
+  // register e of block (bi, bj) -> row lane%16, column 4*(lane/16)+e for the
+  // f32 MFMA and lane/16 + 4*e for the f64 MFMA
+  for (int bi = 0; bi < NB; ++bi)
+    for (int bj = 0; bj < NB; ++bj)
       for (int e = 0; e < 4; ++e) {
-        const int cloc = sizeof(T) == 8 ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e;
-        const int gi = row0 + wr * 64 + bi * 16 + (lane & 15);
-        const int gj = col0 + wc * 64 + bj * 16 + cloc;
+        const int cloc = sizeof(TC) == 8 ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e;
+        const int gi = row0 + wr * WT + bi * 16 + (lane & 15);
+        const int gj = col0 + wc * WT + bj * 16 + cloc;
         if (gi >= d.M || gj >= d.N) continue;
         put<T>(d, z, gi, gj, (double)acc[bi][bj][e], splits, split, part);
       }
 }
 
-template <typename T>
-__global__ void gemm_reduce_kernel(GemmDesc<T> d, int splits, const double* part) {
-  const int64_t mn = (int64_t)d.M * d.N;
-  const int64_t total = mn * d.Z;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int z = (int)(idx / mn);
-    const int64_t e = idx % mn;
-    const int gi = (int)(e % d.M), gj = (int)(e / d.M);
-    if (d.sym && gi > gj) continue;
-    double s = 0.0;
-    for (int k = 0; k < splits; ++k) s += part[(((int64_t)k * d.Z + z) * d.N + gj) * d.M + gi];
-    put<T>(d, z, gi, gj, s, 1, 0, nullptr);
+// ---------------------------------------------------------------------------
+// Mode products of the float32 form with the n x n factor resident in LDS
+// (n <= 128), persistent workgroups of 4 waves, each wave streaming 16-row
+// (or 16-column) strips of the tensor straight from HBM into MFMA operands.
+// Padding of the LDS rows keeps the 64-lane operand reads free of bank
+// conflicts.
+
+// dst_z[a, j] = sum_k src_z[a, k] S[j, k]; src_z, dst_z inner x n (a fastest).
+// A wave takes 16-row strips in turn and fetches the next strip's operands
+// into registers while the MFMAs of the current one run.  The factor goes
+// first into the MFMA, so result blocks are dst^T and the stores of 16 lanes
+// run along a.
+template <int NP>
+__global__ __launch_bounds__(256) void mode_product_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                                           const float* __restrict__ S, int n, int64_t inner,
+                                                           int64_t Z, int64_t strips_per_z) {
+  constexpr int NB = NP / 16, KS = NP / 4;
+  constexpr int SP = NP + ((NP % 32) == 0 ? 16 : 0);   // row stride = 16 mod 32
+  __shared__ float Sl[NP * SP];                         // Sl[k * SP + j] = S[j, k]
+  for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
+    const int j = idx % NP, k = idx / NP;
+    Sl[k * SP + j] = (j < n && k < n) ? S[j + (int64_t)k * n] : 0.f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int64_t total = strips_per_z * Z;
+  float y[KS], yn[KS];
+  // 32-bit byte offsets inside one slice (inner * n < 2^30 is checked by
+  // the launcher).  Rows past the end and k >= n read clamped, in-range
+  // entries instead of being masked: rows past the end are never stored, and
+  // the factor's rows k >= n are zero in LDS.
+  auto fetch = [&](int64_t st, float* v) {
+    const int64_t z = st / strips_per_z;
+    const int64_t r = (st % strips_per_z) * 16 + r16;
+    const uint32_t row = (uint32_t)(r < inner ? r : inner - 1);
+    const char* base = (const char*)(src + z * inner * n);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const uint32_t k = (uint32_t)min(ks * 4 + kq, n - 1);
+      // byte offset within the slice fits 32 bits: scalar base + vector offset
+      v[ks] = *(const float*)(base + (row + k * (uint32_t)inner) * 4u);
+    }
+  };
+  // the strip index is wave-uniform: keep it (and every base address) scalar
+  int64_t st = blockIdx.x * (int64_t)(blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (st < total) fetch(st, y);
+  for (; st < total; st += nwaves) {
+    const int64_t nx = st + nwaves;
+    if (nx < total) fetch(nx, yn);
+    f4 acc[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[cb] = f4{0.f, 0.f, 0.f, 0.f};
+    // an opaque zero keeps the factor reads inside the loop (hoisting all of
+    // them out of the strip loop would need NP^2/16 registers per lane)
+    int opq = 0;
+    asm volatile("" : "+v"(opq));
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const float* Sk = Sl + opq + (ks * 4 + kq) * SP + r16;
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Sk[cb * 16], y[ks], acc[cb], 0, 0, 0);
+    }
+    // block cb, register e: row a0 + r16, column 16 cb + 4 kq + e
+    const int64_t z = st / strips_per_z;
+    const int64_t row = (st % strips_per_z) * 16 + r16;
+    if (row < inner) {
+      float* Cz = dst + z * inner * n + row;
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int col = cb * 16 + 4 * kq + e;
+          if (col < n) Cz[(int64_t)col * inner] = acc[cb][e];
+        }
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) y[ks] = yn[ks];
   }
 }
 
-// Optional timing of every gemm_kernel launch with HIP events on the launch
-// stream (process-wide), used to report the achieved MFMA rate.
+// dst[j, b] = sum_k S[j, k] src[k, b]; src, dst n x outer (the leading leg).
+// Each lane reads 4 consecutive k of one column (one 16-byte load when
+// n % 4 == 0); the MFMA's reduction index is permuted accordingly (lane
+// group kq supplies k = 16 kb + 4 kq + t at step t, and reads the same k of
+// the factor), and the result blocks are dst^T, so stores run along j.
+// 16-column strips, next strip fetched during the current one's MFMAs.
+template <int NP, bool VEC>
+__global__ __launch_bounds__(256) void mode_product_lead_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                                                const float* __restrict__ S, int n, int64_t outer) {
+  constexpr int NB = NP / 16, KB = NP / 16;
+  constexpr int SP = NP + ((NP % 8) == 0 ? 4 : 0);    // row stride = 4 mod 8
+  __shared__ float Sl[NP * SP];                        // Sl[k * SP + j] = S[j, k]
+  for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
+    const int j = idx % NP, k = idx / NP;
+    Sl[k * SP + j] = (j < n && k < n) ? S[j + (int64_t)k * n] : 0.f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int64_t total = ceil_div(outer, 16);
+  f4 x[KB], xn[KB];
+  auto fetch = [&](int64_t st, f4* v) {
+    const int64_t col = st * 16 + r16;
+    const float* p = src + col * n + 4 * kq;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int k = kb * 16 + 4 * kq;
+      f4 w{0.f, 0.f, 0.f, 0.f};
+      if (col < outer) {
+        if (VEC) {
+          if (k < n) w = *(const f4*)(p + kb * 16);
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (k + t < n) w[t] = p[kb * 16 + t];
+        }
+      }
+      v[kb] = w;
+    }
+  };
+  int64_t st = blockIdx.x * (int64_t)(blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (st < total) fetch(st, x);
+  for (; st < total; st += nwaves) {
+    const int64_t nx = st + nwaves;
+    if (nx < total) fetch(nx, xn);
+    f4 acc[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[cb] = f4{0.f, 0.f, 0.f, 0.f};
+    int opq = 0;  // keeps the factor reads inside the strip loop
+    asm volatile("" : "+v"(opq));
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float* Sk = Sl + opq + (kb * 16 + 4 * kq + t) * SP + r16;
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[kb][t], Sk[cb * 16], acc[cb], 0, 0, 0);
+      }
+    // block cb, register e: dst[16 cb + r16, b0 + 4 kq + e]
+    const int64_t b0 = st * 16;
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      const int j = cb * 16 + r16;
+      if (j >= n) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t col = b0 + 4 * kq + e;
+        if (col < outer) dst[j + col * n] = acc[cb][e];
+      }
+    }
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) x[kb] = xn[kb];
+  }
+}
+
+// Leg Gram of the float32 form: out[i, j] = sum over every other index of
+// psi[.., i, ..] cur[.., j, ..] (n <= 128).  Each workgroup reduces a range
+// of depth-16 chunks into the whole padded n x n block (four waves, 2 x 2
+// quadrants of 16 x 16 MFMA blocks) and writes a float64 partial; a second
+// pass sums the partials in a fixed order.  Chunk c covers 16 consecutive a
+// of slice r (a fastest, stride 1: 16-byte loads of 4 a per lane), or, for
+// the leading leg (inner == 1), 16 consecutive b with i fastest.  The MFMA's
+// reduction index is permuted consistently on both operands.
+template <int NP, bool LEAD, bool VEC>
+__global__ __launch_bounds__(256) void leg_gram_kernel(const float* __restrict__ psi, const float* __restrict__ cur,
+                                                       int n, int64_t inner, int64_t outer, int64_t chunks_per_r,
+                                                       int64_t chunks_per_wg, double* __restrict__ part) {
+  constexpr int NB = NP / 16, HB = (NB + 1) / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r16 = lane & 15, kq = lane >> 4;
+  const int ib0 = (wave >> 1) * HB, jb0 = (wave & 1) * HB;
+  f4 acc[HB][HB];
+#pragma unroll
+  for (int x = 0; x < HB; ++x)
+#pragma unroll
+    for (int y = 0; y < HB; ++y) acc[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+  const int64_t total = (LEAD ? 1 : outer) * chunks_per_r;
+  const int64_t c0 = blockIdx.x * chunks_per_wg;
+  const int64_t c1 = c0 + chunks_per_wg < total ? c0 + chunks_per_wg : total;
+  auto load = [&](const float* T, int64_t c, int col) -> f4 {
+    f4 v{0.f, 0.f, 0.f, 0.f};
+    if (col >= n) return v;
+    if (LEAD) {
+      // k = 4 t + kq at step t: T[col, b0 + 4 t + kq], T is n x outer
+      const int64_t b0 = c * 16 + kq;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (b0 + 4 * t < outer) v[t] = T[col + (b0 + 4 * t) * n];
+    } else {
+      // k = 4 kq + t at step t: T[a0 + 4 kq + t, col, r], T is inner x n x outer
+      const int64_t r = c / chunks_per_r;
+      const int64_t a = (c % chunks_per_r) * 16 + 4 * kq;
+      const float* p = T + (r * n + col) * inner + a;
+      if (VEC) {
+        if (a < inner) v = *(const f4*)p;
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (a + t < inner) v[t] = p[t];
+      }
+    }
+    return v;
+  };
+  for (int64_t c = c0; c < c1; ++c) {
+    f4 xa[HB], yb[HB];
+#pragma unroll
+    for (int x = 0; x < HB; ++x) xa[x] = load(psi, c, (ib0 + x) * 16 + r16);
+#pragma unroll
+    for (int y = 0; y < HB; ++y) yb[y] = load(cur, c, (jb0 + y) * 16 + r16);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int x = 0; x < HB; ++x) {
+        if (ib0 + x >= NB) continue;
+#pragma unroll
+        for (int y = 0; y < HB; ++y) {
+          if (jb0 + y >= NB) continue;
+          // cur first: the block is out^T, so lanes run along i
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(yb[y][t], xa[x][t], acc[x][y], 0, 0, 0);
+        }
+      }
+  }
+  // block (x, y), register e: out[16 (ib0 + x) + r16, 16 (jb0 + y) + 4 kq + e]
+  double* out = part + (int64_t)blockIdx.x * n * n;
+#pragma unroll
+  for (int x = 0; x < HB; ++x)
+#pragma unroll
+    for (int y = 0; y < HB; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = (ib0 + x) * 16 + r16, j = (jb0 + y) * 16 + 4 * kq + e;
+        if (ib0 + x < NB && jb0 + y < NB && i < n && j < n) out[(int64_t)j * n + i] = (double)acc[x][y][e];
+      }
+}
+
+// sum of the split partials: 64 consecutive outputs per block, 16 groups of
+// splits per output (fixed order, then a fixed LDS tree): deterministic
+template <typename T>
+__global__ __launch_bounds__(1024) void gemm_reduce_kernel(GemmDesc<T> d, int splits, const double* part) {
+  __shared__ double red[16][65];
+  const int64_t mn = (int64_t)d.M * d.N;
+  const int64_t total = mn * d.Z;
+  const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t idx = blockIdx.x * (int64_t)64 + el;
+  double acc = 0.0;
+  if (idx < total) {
+    const int z = (int)(idx / mn);
+    const int64_t e = idx % mn;
+    const int gi = (int)(e % d.M), gj = (int)(e / d.M);
+    for (int k = g; k < splits; k += 16) acc += part[(((int64_t)k * d.Z + z) * d.N + gj) * d.M + gi];
+  }
+  red[g][el] = acc;
+  __syncthreads();
+  if (g == 0 && idx < total) {
+    double s = 0.0;
+    for (int q = 0; q < 16; ++q) s += red[q][el];
+    const int z = (int)(idx / mn);
+    const int64_t e = idx % mn;
+    const int gi = (int)(e % d.M), gj = (int)(e / d.M);
+    if (!(d.sym && gi > gj)) put<T>(d, z, gi, gj, s, 1, 0, nullptr);
+  }
+}
+
+// Optional timing of every contraction launch with HIP events on the launch
+// stream (process-wide), per kernel kind, for the roofline report.
 constexpr int PROF_CAP = 4096;
+constexpr int PROF_KINDS = 4;   // 0 gemm_pipe_kernel, 1 its float64-accumulated Gram, 2 mode_product_kernel, 3 leg_gram_kernel
 struct GemmProfile {
   int on = 0;
   int n = 0;
   hipEvent_t ev[2 * PROF_CAP];
-  double launches = 0, ms = 0, flops = 0, bytes = 0;
+  int kind[PROF_CAP];
+  double launches[PROF_KINDS] = {}, ms[PROF_KINDS] = {}, flops[PROF_KINDS] = {}, bytes[PROF_KINDS] = {};
 };
 GemmProfile g_prof;
 
@@ -333,9 +475,30 @@ int prof_drain() {
       set_hip_error(e, "gemm profile events");
       return -3;
     }
-    g_prof.ms += t;
+    g_prof.ms[g_prof.kind[i]] += t;
   }
   g_prof.n = 0;
+  return 0;
+}
+
+int prof_begin(hipStream_t s) {
+  if (!g_prof.on) return 0;
+  if (g_prof.n == PROF_CAP) {
+    const int r = prof_drain();
+    if (r) return r;
+  }
+  HPT_HIP(hipEventRecord(g_prof.ev[2 * g_prof.n], s));
+  return 0;
+}
+
+int prof_end(hipStream_t s, int kind, double flops, double bytes) {
+  if (!g_prof.on) return 0;
+  HPT_HIP(hipEventRecord(g_prof.ev[2 * g_prof.n + 1], s));
+  g_prof.kind[g_prof.n] = kind;
+  g_prof.n++;
+  g_prof.launches[kind] += 1;
+  g_prof.flops[kind] += flops;
+  g_prof.bytes[kind] += bytes;
   return 0;
 }
 
@@ -352,19 +515,24 @@ int gemm_profile(int enable) {
     g_prof.on = 0;
     if (r) return r;
   }
-  g_prof.launches = g_prof.ms = g_prof.flops = g_prof.bytes = 0;
+  for (int k = 0; k < PROF_KINDS; ++k) g_prof.launches[k] = g_prof.ms[k] = g_prof.flops[k] = g_prof.bytes[k] = 0;
   return 0;
 }
 
-int gemm_profile_read(double* out4) {
+int gemm_profile_read(int kind, double* out4) {
+  if (kind < -1 || kind >= PROF_KINDS) return -1;
   if (g_prof.on) {
     int r = prof_drain();
     if (r) return r;
   }
-  out4[0] = g_prof.launches;
-  out4[1] = g_prof.ms;
-  out4[2] = g_prof.flops;
-  out4[3] = g_prof.bytes;
+  for (int q = 0; q < 4; ++q) out4[q] = 0;
+  for (int k = 0; k < PROF_KINDS; ++k) {
+    if (kind >= 0 && k != kind) continue;
+    out4[0] += g_prof.launches[k];
+    out4[1] += g_prof.ms[k];
+    out4[2] += g_prof.flops[k];
+    out4[3] += g_prof.bytes[k];
+  }
   return 0;
 }
 
@@ -372,13 +540,13 @@ template <typename T>
 int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.Z <= 0) return 0;
   if (d.K <= 0 || d.R <= 0) return -1;  // callers never ask for an empty reduction
-  // 64 x 64 tiles; HPT_GEMM_TILE=128 selects the 128 x 128 variant (tuning)
+  // 64 x 64 tiles; HPT_GEMM_TILE=128 selects 128 x 128 tiles (tuning)
   static const int forced = [] {
     const char* e = getenv("HPT_GEMM_TILE");
     return e ? atoi(e) : 0;
   }();
   const bool big = !d.acc64 && forced == 128;
-  const int tile = big ? BT : TM;
+  const int tile = big ? 128 : 64;
   const int tiles_m = (int)ceil_div(d.M, tile), tiles_n = (int)ceil_div(d.N, tile);
   if (d.sym && d.M != d.N) return -1;
   const int64_t tiles = (d.sym ? (int64_t)tiles_m * (tiles_m + 1) / 2 : (int64_t)tiles_m * tiles_n) * d.Z;
@@ -391,39 +559,30 @@ int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
   while (tiles * splits < want && total / (splits * 2) >= 8) splits *= 2;
   while (splits > 1 && (int64_t)splits * d.Z * d.M * d.N > part_cap) splits /= 2;
   dim3 grid((unsigned)tiles, (unsigned)splits);
-  const bool prof = g_prof.on;
-  if (prof) {
-    if (g_prof.n == PROF_CAP) {
-      const int r = prof_drain();
-      if (r) return r;
-    }
-    HPT_HIP(hipEventRecord(g_prof.ev[2 * g_prof.n], s));
-  }
+  RC_PROF(prof_begin(s));
   if (d.acc64 && sizeof(T) == 4)
-    hipLaunchKernelGGL((gemm_kernel<T, double>), grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
+    hipLaunchKernelGGL((gemm_pipe_kernel<T, double, 32>), grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
                        chunks_per_r, part);
   else if (big)
-    hipLaunchKernelGGL(gemm_big_kernel<T>, grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
+    hipLaunchKernelGGL((gemm_pipe_kernel<T, T, 64>), grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
                        chunks_per_r, part);
   else
-    hipLaunchKernelGGL((gemm_kernel<T, T>), grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
+    hipLaunchKernelGGL((gemm_pipe_kernel<T, T, 32>), grid, dim3(256), 0, s, d, tiles_m, tiles_n, splits,
                        chunks_per_r, part);
   HPT_LAUNCH_CHECK("gemm_kernel");
-  if (prof) {
-    HPT_HIP(hipEventRecord(g_prof.ev[2 * g_prof.n + 1], s));
-    g_prof.n++;
-    g_prof.launches += 1;
+  {
     const double M = d.M, N = d.N, K = d.K, R = d.R, Z = d.Z;
-    g_prof.flops += (d.sym ? 1.0 : 2.0) * M * N * K * R * Z;  // algorithmic: a SYRK does half
     const double za = d.sAz ? Z : 1.0, zb = d.sBz ? Z : 1.0;
     const double ra = d.sAr ? R : 1.0, rb = d.sBr ? R : 1.0;
-    g_prof.bytes += sizeof(T) * (M * K * ra * za + K * N * rb * zb) +
-                    (d.c_double ? 8.0 : (double)sizeof(T)) * M * N * Z;
+    // algorithmic: a SYRK does half the products; operands read once, result written once
+    RC_PROF(prof_end(s, d.acc64 ? 1 : 0, (d.sym ? 1.0 : 2.0) * M * N * K * R * Z,
+                     sizeof(T) * (M * K * ra * za + K * N * rb * zb) + (d.c_double ? 8.0 : (double)sizeof(T)) * M * N * Z));
   }
   if (splits > 1) {
     const int64_t n = (int64_t)d.M * d.N * d.Z;
-    const int blocks = (int)(ceil_div(n, 256) < 65536 ? ceil_div(n, 256) : 65536);
-    hipLaunchKernelGGL(gemm_reduce_kernel<T>, dim3(blocks), dim3(256), 0, s, d, splits, part);
+    const int64_t blocks = ceil_div(n, 64);
+    if (blocks > 0x7fffffff) return -1;
+    hipLaunchKernelGGL(gemm_reduce_kernel<T>, dim3((unsigned)blocks), dim3(1024), 0, s, d, splits, part);
     HPT_LAUNCH_CHECK("gemm_reduce_kernel");
   }
   return 0;
@@ -431,5 +590,118 @@ int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
 
 template int gemm<double>(const GemmDesc<double>&, double*, int64_t, hipStream_t);
 template int gemm<float>(const GemmDesc<float>&, double*, int64_t, hipStream_t);
+
+namespace {
+int resident_grid(const void* kernel, int threads, int64_t work_waves) {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  const int64_t need = ceil_div(work_waves, threads / 64);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * per_cu));
+}
+
+template <int NP>
+int launch_mode(const float* src, float* dst, const float* S, int n, int64_t inner, int64_t outer, hipStream_t s) {
+  if (inner == 1) {
+    const int64_t strips = ceil_div(outer, 16);
+    if (n % 4 == 0) {
+      const int g = resident_grid((const void*)mode_product_lead_kernel<NP, true>, 256, strips);
+      hipLaunchKernelGGL((mode_product_lead_kernel<NP, true>), dim3(g), dim3(256), 0, s, src, dst, S, n, outer);
+    } else {
+      const int g = resident_grid((const void*)mode_product_lead_kernel<NP, false>, 256, strips);
+      hipLaunchKernelGGL((mode_product_lead_kernel<NP, false>), dim3(g), dim3(256), 0, s, src, dst, S, n, outer);
+    }
+  } else {
+    const int64_t spz = ceil_div(inner, 16);
+    const int g = resident_grid((const void*)mode_product_kernel<NP>, 256, spz * outer);
+    hipLaunchKernelGGL((mode_product_kernel<NP>), dim3(g), dim3(256), 0, s, src, dst, S, n, inner, outer, spz);
+  }
+  HPT_LAUNCH_CHECK("mode_product_kernel");
+  return 0;
+}
+template <int NP>
+int launch_leg_gram(const float* psi, const float* cur, int n, int64_t inner, int64_t outer, int64_t chunks_per_r,
+                    int64_t cpw, int G, double* part, hipStream_t s) {
+  if (inner == 1)
+    hipLaunchKernelGGL((leg_gram_kernel<NP, true, false>), dim3(G), dim3(256), 0, s, psi, cur, n, inner, outer,
+                       chunks_per_r, cpw, part);
+  else if (inner % 4 == 0)
+    hipLaunchKernelGGL((leg_gram_kernel<NP, false, true>), dim3(G), dim3(256), 0, s, psi, cur, n, inner, outer,
+                       chunks_per_r, cpw, part);
+  else
+    hipLaunchKernelGGL((leg_gram_kernel<NP, false, false>), dim3(G), dim3(256), 0, s, psi, cur, n, inner, outer,
+                       chunks_per_r, cpw, part);
+  HPT_LAUNCH_CHECK("leg_gram_kernel");
+  return 0;
+}
+}  // namespace
+
+int leg_gram_f32(const float* psi, const float* cur, int n, int64_t inner, int64_t outer, double* out, double* part,
+                 int64_t part_cap, hipStream_t s) {
+  if (n < 1 || n > 128 || inner < 1 || outer < 1) return 0;
+  const int64_t n2 = (int64_t)n * n;
+  const int64_t chunks_per_r = inner == 1 ? ceil_div(outer, 16) : ceil_div(inner, 16);
+  const int64_t total = (inner == 1 ? 1 : outer) * chunks_per_r;
+  int64_t G = std::min<int64_t>(1024, part_cap / n2);
+  G = std::min<int64_t>(G, total);
+  if (G < 1) return 0;
+  const int64_t cpw = ceil_div(total, G);
+  G = ceil_div(total, cpw);
+  RC_PROF(prof_begin(s));
+  int r;
+  switch ((n + 15) / 16) {
+    case 1: r = launch_leg_gram<16>(psi, cur, n, inner, outer, chunks_per_r, cpw, (int)G, part, s); break;
+    case 2: r = launch_leg_gram<32>(psi, cur, n, inner, outer, chunks_per_r, cpw, (int)G, part, s); break;
+    case 3: r = launch_leg_gram<48>(psi, cur, n, inner, outer, chunks_per_r, cpw, (int)G, part, s); break;
+    case 4: r = launch_leg_gram<64>(psi, cur, n, inner, outer, chunks_per_r, cpw, (int)G, part, s); break;
+    case 5: r = launch_leg_gram<80>(psi, cur, n, inner, outer, chunks_per_r, cpw, (int)G, part, s); break;
+    case 6: r = launch_leg_gram<96>(psi, cur, n, inner, outer, chunks_per_r, cpw, (int)G, part, s); break;
+    case 7: r = launch_leg_gram<112>(psi, cur, n, inner, outer, chunks_per_r, cpw, (int)G, part, s); break;
+    default: r = launch_leg_gram<128>(psi, cur, n, inner, outer, chunks_per_r, cpw, (int)G, part, s); break;
+  }
+  if (r) return r;
+  {
+    const double el = (double)inner * n * outer;
+    RC_PROF(prof_end(s, 3, 2.0 * el * n, 4.0 * 2.0 * el + 8.0 * n2));
+  }
+  GemmDesc<float> d{};
+  d.M = n; d.N = n; d.K = 1; d.R = 1; d.Z = 1;
+  d.C = out; d.ldc = n; d.c_double = 1; d.alpha = 1.0; d.beta = 0.0;
+  const int64_t blocks = ceil_div(n2, 64);
+  hipLaunchKernelGGL(gemm_reduce_kernel<float>, dim3((unsigned)blocks), dim3(1024), 0, s, d, (int)G, (const double*)part);
+  HPT_LAUNCH_CHECK("gemm_reduce_kernel");
+  return 1;
+}
+
+int mode_product_f32(const float* S, const float* src, float* dst, int n, int64_t inner, int64_t outer,
+                     hipStream_t s) {
+  if (n < 1 || n > 128 || inner < 1 || outer < 1) return 0;
+  if (inner > 1 && inner < 16) return 0;
+  if (inner * n >= ((int64_t)1 << 30)) return 0;  // 32-bit byte offsets inside a slice
+  if (inner == 1 && outer < 16) return 0;
+  RC_PROF(prof_begin(s));
+  int r;
+  switch ((n + 15) / 16) {
+    case 1: r = launch_mode<16>(src, dst, S, n, inner, outer, s); break;
+    case 2: r = launch_mode<32>(src, dst, S, n, inner, outer, s); break;
+    case 3: r = launch_mode<48>(src, dst, S, n, inner, outer, s); break;
+    case 4: r = launch_mode<64>(src, dst, S, n, inner, outer, s); break;
+    case 5: r = launch_mode<80>(src, dst, S, n, inner, outer, s); break;
+    case 6: r = launch_mode<96>(src, dst, S, n, inner, outer, s); break;
+    case 7: r = launch_mode<112>(src, dst, S, n, inner, outer, s); break;
+    default: r = launch_mode<128>(src, dst, S, n, inner, outer, s); break;
+  }
+  if (r) return r;
+  const double el = (double)inner * n * outer;
+  RC_PROF(prof_end(s, 2, 2.0 * el * n, 4.0 * (2.0 * el + (double)n * n)));
+  return 1;
+}
+
+
 
 }  // namespace hpt

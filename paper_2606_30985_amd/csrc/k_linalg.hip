@@ -16,6 +16,13 @@ namespace hpt {
 
 namespace {
 
+// gate semantics of the batched jobs: no gate -> run; gate_zero -> run when
+// *gate == 0; otherwise run when *gate != 0
+__device__ inline bool gated_out(const int* gate, int gate_zero) {
+  if (!gate) return false;
+  return gate_zero ? (*gate != 0) : (*gate == 0);
+}
+
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -180,7 +187,7 @@ __global__ __launch_bounds__(256) void pseudo_sqrt_kernel(const PsqJob* jobs, do
 template <typename T>
 __global__ __launch_bounds__(256) void householder_kernel(const QrJob<T>* jobs) {
   const QrJob<T> job = jobs[blockIdx.x];
-  if (job.gate && *job.gate == 0) return;
+  if (gated_out(job.gate, job.gate_zero)) return;
   const int m = job.m, n = job.n, k = m < n ? m : n;
   T* A = job.A;
   const int64_t lda = job.lda;
@@ -351,11 +358,153 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdJob* jobs) {
 }
 
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Block one-sided Jacobi SVD.  Columns are grouped in blocks of w; a round
+// pairs blocks by the circle method, and each workgroup takes one block pair
+// of one job: it loads the 2w columns into LDS, runs one inner Jacobi sweep
+// over all their pairs (one wave per pair), accumulates the 2w x 2w rotation
+// J, writes the columns back and applies J to the same columns of V.
+__global__ void bj_init_kernel(const SvdJob* jobs) {
+  const SvdJob job = jobs[blockIdx.x];
+  for (int idx = threadIdx.x; idx < job.n * job.n; idx += blockDim.x) {
+    const int i = idx % job.n, j = idx / job.n;
+    job.V[i + (int64_t)j * job.ldv] = (i == j) ? 1.0 : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    job.state[0] = job.n < 2;
+    job.state[1] = 0;
+    job.state[2] = 0;
+    if (job.sweeps) *job.sweeps = 0;
+  }
+}
+
+__global__ void bj_sweep_begin_kernel(const SvdJob* jobs, int sweep) {
+  const SvdJob job = jobs[blockIdx.x];
+  if (threadIdx.x != 0 || job.state[0]) return;
+  if (sweep > 0 && job.state[1 + ((sweep - 1) & 1)] == 0) {
+    job.state[0] = 1;
+    return;
+  }
+  job.state[1 + (sweep & 1)] = 0;
+  if (job.sweeps) *job.sweeps = sweep + 1;
+}
+
+__global__ __launch_bounds__(1024) void bj_round_kernel(const SvdJob* jobs, int round, int sweep, int w) {
+  const SvdJob job = jobs[blockIdx.y];
+  if (job.state[0]) return;
+  const int m = job.m, n = job.n;
+  const int nb = (n + w - 1) / w, nb2 = nb + (nb & 1);
+  if (round >= nb2 - 1 || (int)blockIdx.x >= nb2 / 2) return;
+  int P, Q;
+  rr_pair(round, blockIdx.x, nb2, P, Q);
+  if (P >= nb || Q >= nb) return;
+  extern __shared__ double lds[];
+  const int W2 = 2 * w;
+  double* J = lds;                 // W2 x W2, J[u + W2 t]
+  double* Gs = lds + W2 * W2;      // column t at Gs + t * m
+  __shared__ int cols[64];
+  __shared__ int s_nc, s_rot;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  if (tid == 0) {
+    int nc = 0;
+    for (int t = 0; t < w; ++t)
+      if (P * w + t < n) cols[nc++] = P * w + t;
+    for (int t = 0; t < w; ++t)
+      if (Q * w + t < n) cols[nc++] = Q * w + t;
+    s_nc = nc;
+    s_rot = 0;
+  }
+  __syncthreads();
+  const int nc = s_nc;
+  for (int idx = tid; idx < nc * m; idx += blockDim.x) {
+    const int t = idx / m, i = idx % m;
+    Gs[idx] = job.G[i + (int64_t)cols[t] * job.ldg];
+  }
+  for (int idx = tid; idx < W2 * W2; idx += blockDim.x) J[idx] = (idx % W2 == idx / W2) ? 1.0 : 0.0;
+  __syncthreads();
+  const double tol = 1e-15 * sqrt((double)m);
+  const int nc2 = nc + (nc & 1);
+  for (int r = 0; r < nc2 - 1; ++r) {
+    for (int k = wave; k < nc2 / 2; k += nw) {
+      int a, b;
+      rr_pair(r, k, nc2, a, b);
+      if (a >= nc || b >= nc) continue;
+      double* ga = Gs + a * m;
+      double* gb = Gs + b * m;
+      double x2 = 0.0, y2 = 0.0, xy = 0.0;
+      for (int i = lane; i < m; i += 64) {
+        const double x = ga[i], y = gb[i];
+        x2 += x * x;
+        y2 += y * y;
+        xy += x * y;
+      }
+      x2 = wave_sum(x2);
+      y2 = wave_sum(y2);
+      xy = wave_sum(xy);
+      if (xy == 0.0 || !(fabs(xy) > tol * sqrt(x2 * y2))) continue;
+      double c, sn;
+      jacobi_rotation(x2, y2, xy, c, sn);
+      for (int i = lane; i < m; i += 64) {
+        const double x = ga[i], y = gb[i];
+        ga[i] = c * x - sn * y;
+        gb[i] = sn * x + c * y;
+      }
+      for (int u = lane; u < W2; u += 64) {
+        const double x = J[u + W2 * a], y = J[u + W2 * b];
+        J[u + W2 * a] = c * x - sn * y;
+        J[u + W2 * b] = sn * x + c * y;
+      }
+      if (lane == 0) s_rot = 1;
+    }
+    __syncthreads();
+  }
+  if (!s_rot) return;
+  for (int idx = tid; idx < nc * m; idx += blockDim.x) {
+    const int t = idx / m, i = idx % m;
+    job.G[i + (int64_t)cols[t] * job.ldg] = Gs[idx];
+  }
+  // V[:, cols] <- V[:, cols] J, one row per thread
+  for (int i = tid; i < n; i += blockDim.x) {
+    double row[32];
+    for (int u = 0; u < nc; ++u) row[u] = job.V[i + (int64_t)cols[u] * job.ldv];
+    for (int t = 0; t < nc; ++t) {
+      double acc = 0.0;
+      for (int u = 0; u < nc; ++u) acc += row[u] * J[u + W2 * t];
+      job.V[i + (int64_t)cols[t] * job.ldv] = acc;
+    }
+  }
+  if (tid == 0) atomicAdd(&job.state[1 + (sweep & 1)], 1);
+}
+
+__global__ __launch_bounds__(1024) void bj_finish_kernel(const SvdJob* jobs) {
+  const SvdJob job = jobs[blockIdx.x];
+  const int m = job.m, n = job.n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  __shared__ double s_sig[1024];
+  for (int p = wave; p < n; p += nw) {
+    double a = 0.0;
+    for (int i = lane; i < m; i += 64) a += job.G[i + (int64_t)p * job.ldg] * job.G[i + (int64_t)p * job.ldg];
+    a = wave_sum(a);
+    if (lane == 0) s_sig[p] = sqrt(a);
+  }
+  __syncthreads();
+  for (int p = tid; p < n; p += blockDim.x) {
+    const double sp = s_sig[p];
+    int rank = 0;
+    for (int q = 0; q < n; ++q) {
+      const double sq = s_sig[q];
+      if (sq > sp || (sq == sp && q < p)) ++rank;
+    }
+    job.perm[rank] = p;
+    job.s[rank] = sp;
+  }
+}
+
 // Left-looking upper Cholesky; at step j every later column i needs the dot
 // of columns j and i above row j: one wave per column, lanes over rows.
 __global__ __launch_bounds__(1024) void cholesky_kernel(const CholJob* jobs, double rel_tol) {
   const CholJob job = jobs[blockIdx.x];
-  if (job.gate && *job.gate == 0) return;
+  if (gated_out(job.gate, job.gate_zero)) return;
   const int n = job.n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   double* R = job.R;
@@ -395,7 +544,10 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(const CholJob* jobs, dou
     }
     __syncthreads();
     if (s_fail) {
-      if (tid == 0) *job.info = s_fail;
+      if (tid == 0) {
+        *job.info = s_fail;
+        if (job.fail) *job.fail = 1;
+      }
       return;
     }
     const double rjj = sh[0];
@@ -530,7 +682,7 @@ __global__ void sel_kernel(const SelJob* jobs) {
 // Rinv = Y^T.
 __global__ __launch_bounds__(1024) void tri_inverse_kernel(const TriInvJob* jobs) {
   const TriInvJob job = jobs[blockIdx.x];
-  if (job.gate && *job.gate == 0) return;
+  if (gated_out(job.gate, job.gate_zero)) return;
   const int n = job.n;
   const double* R = job.R;
   double* Ri = job.Ri;
@@ -556,23 +708,72 @@ __global__ __launch_bounds__(1024) void tri_inverse_kernel(const TriInvJob* jobs
   }
 }
 
-__global__ __launch_bounds__(1024) void small_gemm_kernel(const SmallGemmJob* jobs) {
-  const SmallGemmJob job = jobs[blockIdx.x];
-  if (job.gate && *job.gate == 0) return;
+constexpr int SG = 64;   // output tile side
+constexpr int SGK = 16;  // depth chunk
+
+// Batched C = alpha op(A) op(B) + beta C on the float64 MFMA (16x16x4): a
+// 64 x 64 tile of one job per workgroup, four waves in a 2 x 2 grid with 2 x 2
+// MFMA blocks each, depth-16 chunks of op(A) and op(B) staged in LDS.  Sizes
+// may come from device memory.
+__global__ __launch_bounds__(256) void small_gemm_kernel(const SmallGemmJob* jobs) {
+  const SmallGemmJob job = jobs[blockIdx.y];
+  if (gated_out(job.gate, job.gate_zero)) return;
   const int M = job.M_dev ? *job.M_dev : job.M;
   const int N = job.N_dev ? *job.N_dev : job.N;
   const int K = job.K_dev ? *job.K_dev : job.K;
-  for (int idx = threadIdx.x; idx < M * N; idx += blockDim.x) {
-    const int i = idx % M, j = idx / M;
-    double s = 0.0;
-    for (int k = 0; k < K; ++k) {
-      const double a = job.tA ? job.A[k + (int64_t)i * job.lda] : job.A[i + (int64_t)k * job.lda];
-      const double b = job.tB ? job.B[j + (int64_t)k * job.ldb] : job.B[k + (int64_t)j * job.ldb];
-      s += a * b;
+  const int tiles_m = (M + SG - 1) / SG, tiles_n = (N + SG - 1) / SG;
+  if ((int)blockIdx.x >= tiles_m * tiles_n) return;
+  const int i0 = (blockIdx.x % tiles_m) * SG, j0 = (blockIdx.x / tiles_m) * SG;
+  __shared__ double As[SGK][SG + 1];  // As[k][i] = op(A)(i0 + i, k0 + k)
+  __shared__ double Bs[SGK][SG + 1];  // Bs[k][j] = op(B)(k0 + k, j0 + j)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  d4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < 4; ++e) acc[a][b][e] = 0.0;
+  for (int k0 = 0; k0 < K; k0 += SGK) {
+#pragma unroll
+    for (int q = 0; q < SG * SGK / 256; ++q) {
+      const int e = tid + 256 * q;
+      {
+        // contiguous axis of the stored A: i when not transposed, k otherwise
+        const int i = job.tA ? e / SGK : e % SG, k = job.tA ? e % SGK : e / SG;
+        const int gi = i0 + i, gk = k0 + k;
+        double v = 0.0;
+        if (gi < M && gk < K) v = job.tA ? job.A[gk + (int64_t)gi * job.lda] : job.A[gi + (int64_t)gk * job.lda];
+        As[k][i] = v;
+      }
+      {
+        const int j = job.tB ? e % SG : e / SGK, k = job.tB ? e / SG : e % SGK;
+        const int gj = j0 + j, gk = k0 + k;
+        double v = 0.0;
+        if (gj < N && gk < K) v = job.tB ? job.B[gj + (int64_t)gk * job.ldb] : job.B[gk + (int64_t)gj * job.ldb];
+        Bs[k][j] = v;
+      }
     }
-    double* c = job.C + i + (int64_t)j * job.ldc;
-    *c = job.alpha * s + (job.beta != 0.0 ? job.beta * *c : 0.0);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < SGK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      double a[2], b[2];
+      for (int x = 0; x < 2; ++x) a[x] = As[kr][wr * 32 + x * 16 + (lane & 15)];
+      for (int y = 0; y < 2; ++y) b[y] = Bs[kr][wc * 32 + y * 16 + (lane & 15)];
+      // operands swapped: the result blocks are C^T, so lanes run along C's rows
+      for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[y], a[x], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
   }
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y)
+      for (int e = 0; e < 4; ++e) {
+        const int gi = i0 + wr * 32 + x * 16 + (lane & 15);
+        const int gj = j0 + wc * 32 + y * 16 + (lane >> 4) + 4 * e;
+        if (gi >= M || gj >= N) continue;
+        double* c = job.C + gi + (int64_t)gj * job.ldc;
+        *c = job.alpha * acc[x][y][e] + (job.beta != 0.0 ? job.beta * *c : 0.0);
+      }
 }
 
 }  // namespace
@@ -598,6 +799,44 @@ int launch_jacobi_svd(const SvdJob* jobs, int njobs, hipStream_t s) {
   if (njobs <= 0) return 0;
   hipLaunchKernelGGL(jacobi_svd_kernel, dim3(njobs), dim3(1024), 0, s, jobs);
   HPT_LAUNCH_CHECK("jacobi_svd_kernel");
+  return 0;
+}
+
+int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  int mmax = 1, nmax = 1;
+  for (int j = 0; j < njobs; ++j) {
+    mmax = std::max(mmax, host[j].m);
+    nmax = std::max(nmax, host[j].n);
+  }
+  // block width: 16 columns per block when a pair of blocks fits in the
+  // workgroup's LDS (leaving room for the kernel's static LDS)
+  static int max_lds = 0;
+  if (!max_lds) {
+    int dev = 0;
+    HPT_HIP(hipGetDevice(&dev));
+    HPT_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  }
+  const size_t budget = (size_t)max_lds > 2048 ? (size_t)max_lds - 2048 : 0;
+  int w = 16;
+  while (w > 2 && (size_t)(2 * w * mmax + 4 * w * w) * 8 > budget) w /= 2;
+  const size_t lds = (size_t)(2 * w * mmax + 4 * w * w) * 8;
+  if (lds > budget || njobs > 65535) return -1;
+  const int nb = (nmax + w - 1) / w, nb2 = nb + (nb & 1);
+  hipLaunchKernelGGL(bj_init_kernel, dim3(njobs), dim3(256), 0, s, jobs);
+  HPT_LAUNCH_CHECK("bj_init_kernel");
+  const int max_sweeps = 20;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    hipLaunchKernelGGL(bj_sweep_begin_kernel, dim3(njobs), dim3(64), 0, s, jobs, sweep);
+    HPT_LAUNCH_CHECK("bj_sweep_begin_kernel");
+    for (int r = 0; r < nb2 - 1; ++r) {
+      hipLaunchKernelGGL(bj_round_kernel, dim3(std::max(1, nb2 / 2), njobs), dim3(1024), lds, s, jobs, r,
+                         sweep, w);
+      HPT_LAUNCH_CHECK("bj_round_kernel");
+    }
+  }
+  hipLaunchKernelGGL(bj_finish_kernel, dim3(njobs), dim3(1024), 0, s, jobs);
+  HPT_LAUNCH_CHECK("bj_finish_kernel");
   return 0;
 }
 
@@ -629,9 +868,13 @@ int launch_sel(const SelJob* jobs, int njobs, hipStream_t s) {
   return 0;
 }
 
-int launch_small_gemm(const SmallGemmJob* jobs, int njobs, hipStream_t s) {
+int launch_small_gemm(const SmallGemmJob* jobs, const SmallGemmJob* host, int njobs, hipStream_t s) {
   if (njobs <= 0) return 0;
-  hipLaunchKernelGGL(small_gemm_kernel, dim3(njobs), dim3(1024), 0, s, jobs);
+  int64_t tiles = 1;
+  for (int j = 0; j < njobs; ++j)
+    tiles = std::max<int64_t>(tiles, ceil_div(host[j].M, SG) * ceil_div(host[j].N, SG));
+  if (tiles > 0x7fffffff || njobs > 65535) return -1;
+  hipLaunchKernelGGL(small_gemm_kernel, dim3((unsigned)tiles, njobs), dim3(256), 0, s, jobs);
   HPT_LAUNCH_CHECK("small_gemm_kernel");
   return 0;
 }

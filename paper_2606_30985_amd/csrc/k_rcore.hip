@@ -50,6 +50,38 @@ __global__ __launch_bounds__(256) void build_B_kernel(BondCore* bonds, GateFacto
   }
 }
 
+// B_i[(kk, e), (c, r)] = sum_d Fr[r][e + 4d] R_i[kk, c + chi d], so
+// (B_i^T B_i)[(c, r), (c', r')] = sum_{d, d'} phi[d][d'][r][r'] (R_i^T R_i)[c + chi d, c' + chi d']
+// with phi[d][d'][r][r'] = sum_e Fr[r][e + 4d] Fr[r'][e + 4d'].
+__global__ __launch_bounds__(256) void kron_gram_kernel(BondCore* bonds, GateFactors g) {
+  BondCore& bc = bonds[blockIdx.x];
+  const int i = blockIdx.y;
+  if (bc.bqr[i] != 0) return;
+  const int chi = bc.chi_cut, n = 4 * chi;
+  const double(*Fr)[16] = (i == 0) ? g.F : g.H;
+  __shared__ double phi[256];
+  for (int t = threadIdx.x; t < 256; t += blockDim.x) {
+    const int d = t & 3, d2 = (t >> 2) & 3, r = (t >> 4) & 3, r2 = t >> 6;
+    double v = 0.0;
+    for (int e = 0; e < 4; ++e) v += Fr[r][e + 4 * d] * Fr[r2][e + 4 * d2];
+    phi[t] = v;
+  }
+  __syncthreads();
+  const double* RtR = bc.qs[i][5];
+  double* GB = bc.qs[i][0];
+  const int64_t total = (int64_t)n * n;
+  for (int64_t idx = blockIdx.z * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.z * blockDim.x) {
+    const int row = (int)(idx % n), col = (int)(idx / n);
+    const int c = row % chi, r = row / chi, c2 = col % chi, r2 = col / chi;
+    double v = 0.0;
+    for (int d = 0; d < 4; ++d)
+      for (int d2 = 0; d2 < 4; ++d2)
+        v += phi[d + 4 * d2 + 16 * r + 64 * r2] * RtR[(c + chi * d) + (int64_t)(c2 + chi * d2) * n];
+    GB[idx] = v;
+  }
+}
+
 __global__ __launch_bounds__(1024) void select_kernel(BondCore* bonds) {
   BondCore& bc = bonds[blockIdx.x];
   __shared__ double sh[16];
@@ -175,6 +207,12 @@ int launch_rcore_build_B(BondCore* bonds, int nb, const GateFactors& g, hipStrea
   if (nb <= 0) return 0;
   hipLaunchKernelGGL(build_B_kernel, dim3(nb, 2), dim3(256), 0, s, bonds, g);
   HPT_LAUNCH_CHECK("build_B_kernel");
+  return 0;
+}
+int launch_rcore_kron_gram(BondCore* bonds, int nb, const GateFactors& g, hipStream_t s) {
+  if (nb <= 0) return 0;
+  hipLaunchKernelGGL(kron_gram_kernel, dim3(nb, 2, 32), dim3(256), 0, s, bonds, g);
+  HPT_LAUNCH_CHECK("kron_gram_kernel");
   return 0;
 }
 int launch_rcore_select(BondCore* bonds, int nb, hipStream_t s) {

@@ -28,6 +28,7 @@ struct QrJob {
   double* tau;         // n scratch
   int form_q;
   const int* gate;
+  int gate_zero;       // 1: run only when *gate == 0
 };
 
 // One-sided Jacobi SVD of an m x n (m >= n) float64 block in place.
@@ -38,6 +39,7 @@ struct SvdJob {
   double* V; int ldv;
   double* s; int* perm;
   int* sweeps;
+  int* state;          // 3 ints of scratch for the block variant (done, 2 rotation counters)
 };
 
 // Upper Cholesky G = R^T R of an n x n SPD block (G read, R written, may alias).
@@ -47,6 +49,8 @@ struct CholJob {
   double* R; int ldr;
   int* info;
   const int* gate;     // skip when *gate == 0 (null = always run)
+  int gate_zero;       // 1: run only when *gate == 0 instead
+  int* fail;           // optional: set to 1 when the factorisation fails
 };
 
 // Cholesky with diagonal pivoting of an n x n PSD Gram matrix, stopped when
@@ -75,10 +79,12 @@ struct TriInvJob {
   const double* R; int ldr; int n;
   double* Ri; int ldri;
   const int* gate;
+  int gate_zero;       // 1: run only when *gate == 0
 };
 
 // Small batched float64 GEMM: C = alpha op(A) op(B) + beta C; sizes may be
-// read from device memory (m_ptr etc. override when non-null).
+// read from device memory (M_dev etc. override when non-null; the host
+// fields M, N then hold upper bounds used to size the launch).
 struct SmallGemmJob {
   int M, N, K;
   const int* M_dev; const int* N_dev; const int* K_dev;
@@ -87,16 +93,21 @@ struct SmallGemmJob {
   double* C; int ldc;
   double alpha, beta;
   const int* gate;     // skip when *gate == 0 (null = always run)
+  int gate_zero;       // 1: run only when *gate == 0 instead
 };
 
 int launch_pseudo_sqrt(const PsqJob* jobs, int njobs, double eps_pinv, hipStream_t s);
 template <typename T>
 int launch_householder(const QrJob<T>* jobs, int njobs, hipStream_t s);
 int launch_jacobi_svd(const SvdJob* jobs, int njobs, hipStream_t s);
+// Block one-sided Jacobi: every launch of a round pairs column blocks of all
+// jobs, one workgroup per block pair with the block columns in LDS.  Needs
+// SvdJob::state; host holds the host copies of the jobs (sizes).
+int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, hipStream_t s);
 int launch_cholesky(const CholJob* jobs, int njobs, double rel_tol, hipStream_t s);
 int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s);
 int launch_piv_cholesky(const PivCholJob* jobs, int njobs, hipStream_t s);
 int launch_sel(const SelJob* jobs, int njobs, hipStream_t s);
-int launch_small_gemm(const SmallGemmJob* jobs, int njobs, hipStream_t s);
+int launch_small_gemm(const SmallGemmJob* jobs, const SmallGemmJob* host, int njobs, hipStream_t s);
 
 }  // namespace hpt

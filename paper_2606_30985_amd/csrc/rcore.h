@@ -12,6 +12,7 @@ struct BondCore {
   int k[2];               // rows of R_i = min(m_i, 4 chi_cut)
   int q[2];               // rows of T_i = min(4 k_i, 4 chi_cut)
   int chol[2];            // 1: S_i = X_i and W_i = R_i^{-1} M'_i; 0: S_i = Q_i, W_i = M'_i
+  int bqr[2];             // QR of B_i: 0 CholeskyQR2 (set to 1 when it fails), 1 Householder
   int chi_max;
   double eps_cut;
   const double* R[2];     // k_i x 4 chi_cut, ld ldR
@@ -34,6 +35,7 @@ struct BondCore {
   const double* z;        // sign projections of S_0: n_S_0 x 4
   double* msg[2];         // gauge message slots of this bond (chi_new x chi_new)
   double* lam;            // lambda out (chi_max)
+  double* qs[2][8];       // float64 scratch of the CholeskyQR2 of B_i (4 chi_max x 4 chi_max each)
   // outputs
   int chi_new;
   int n4;                 // 4 * chi_new
@@ -51,6 +53,9 @@ struct GateFactors {
 };
 
 int launch_rcore_build_B(BondCore* bonds, int nb, const GateFactors& g, hipStream_t s);
+// Gram B_i^T B_i of the gated blocks (bqr[i] == 0) from R_i^T R_i in qs[i][5]
+// into qs[i][0]
+int launch_rcore_kron_gram(BondCore* bonds, int nb, const GateFactors& g, hipStream_t s);
 int launch_rcore_select(BondCore* bonds, int nb, hipStream_t s);
 int launch_rcore_rearrange(BondCore* bonds, int nb, hipStream_t s);
 int launch_rcore_signs(BondCore* bonds, int nb, hipStream_t s);

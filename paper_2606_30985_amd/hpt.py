@@ -96,6 +96,7 @@ def _load():
         "hpt_permute": [P, P, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), i32, P],
         "hpt_profile_gemm": [i32],
         "hpt_profile_gemm_read": [ctypes.POINTER(dbl)],
+        "hpt_profile_read": [i32, ctypes.POINTER(dbl)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -115,16 +116,21 @@ EXPORTED = ["hpt_config_default", "hpt_required_bytes", "hpt_state_bytes", "hpt_
             "hpt_measure", "hpt_get_chi", "hpt_get_bond_spectrum", "hpt_get_site_tensor",
             "hpt_set_site_tensor", "hpt_get_messages", "hpt_set_messages",
             "hpt_get_meas_messages", "hpt_destroy", "hpt_strerror", "hpt_last_hip_error",
-            "hpt_permute", "hpt_profile_gemm", "hpt_profile_gemm_read"]
+            "hpt_permute", "hpt_profile_gemm", "hpt_profile_gemm_read", "hpt_profile_read"]
 
 
 def profile_gemm(enable=True):
     check(lib.hpt_profile_gemm(1 if enable else 0), "hpt_profile_gemm")
 
 
-def profile_gemm_read():
+PROF_KINDS = {"gemm": 0, "gram64": 1, "mode": 2, "leggram": 3}
+
+
+def profile_gemm_read(kind=None):
+    """Counters of one contraction kind ("gemm", "gram64", "mode", "leggram") or of all."""
     out = (ctypes.c_double * 4)()
-    check(lib.hpt_profile_gemm_read(out), "hpt_profile_gemm_read")
+    k = -1 if kind is None else PROF_KINDS[kind]
+    check(lib.hpt_profile_read(k, out), "hpt_profile_read")
     return dict(launches=int(out[0]), ms=out[1], flops=out[2], bytes=out[3])
 
 

@@ -22,8 +22,37 @@ CASES = {
     "oracle_3x3_chi8": (dict(Lx=3, Ly=3, J=1.0, h=1.0, dt=0.05, chi_max=8, bp_alpha=0.5, bp_tol=1e-10), 20),
 }
 
+BOND_CASES = ("oracle_bond_4x4_chi100",)
+
+
+def bond_case(name):
+    """One interior-interior bond update at chi = 100 on the seeded saturated
+    state of tests/fullsize_case.py: spectrum, bond dimension, gate error and
+    sampled entries (with norms) of both new site tensors."""
+    import numpy as np
+    from tests import fullsize_case as fc
+    t0 = time.time()
+    net, b = fc.state()
+    print(f"state {time.time() - t0:.1f}s", flush=True)
+    r = net.gate_update(b)
+    print(f"update {time.time() - t0:.1f}s", flush=True)
+    v1, v2, _ = net.lat.bonds[b]
+    sites = {}
+    for v in (v1, v2):
+        flat = net.psi[v].ravel(order="F")
+        idx = fc.sample_index(flat.size)
+        sites[str(v)] = dict(dims=list(net.psi[v].shape), norm=float(np.linalg.norm(flat)),
+                             idx=[int(i) for i in idx], val=[float(x) for x in flat[idx]])
+    out = dict(config=fc.CFG, seed=fc.SEED, bond=int(b), source="oracle/ (CPU FP64 restatement of the method)",
+               chi_new=int(r["chi_new"]), lam=[float(x) for x in r["lam"]], gate_err=float(r["gate_err"]),
+               sites=sites)
+    with open(os.path.join(HERE, name + ".json"), "w") as f:
+        json.dump(out, f)
+
 
 def main(name):
+    if name in BOND_CASES:
+        return bond_case(name)
     cfg, n = CASES[name]
     t0 = time.time()
 
