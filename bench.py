@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--bp-tol", type=float, default=1e-5)
     ap.add_argument("--bp-max-sweeps", type=int, default=100)
     ap.add_argument("--meas-tol", type=float, default=1e-10)
-    ap.add_argument("--meas-max-sweeps", type=int, default=1000)
+    ap.add_argument("--meas-max-sweeps", type=int, default=400)
     ap.add_argument("--bp-init", default="warm", choices=["warm", "uniform"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trace", default="", help="append per-step records (JSON lines) to this file")

@@ -215,7 +215,13 @@ void make_carve(const hpt_config& c, Carve& cv) {
   cv.part_cap = std::max<int64_t>(1 << 22, 64 * n4 * n4);
   cv.part = off; off = align_up(off + cv.part_cap * 8);
   const int maxdeg = std::max(1, [&] { int d = 0; for (auto& s : sites) d = std::max(d, s.deg); return d; }());
-  cv.meas_scr_cap = std::max<int64_t>(1 << 20, 4 * 4 * ipow(C, maxdeg - 1) + 64 * C);
+  // measurement scratch: per site the contracted slice P (chi^(deg-1)), the
+  // block partials of the last leg and the small contraction vectors, for
+  // every site at once
+  int64_t mneed = 0;
+  for (auto& st : sites) mneed += 2 * ipow(C, std::max(st.deg - 1, 0)) + 4 * C * C + 64 * C + 64;
+  cv.meas_scr_cap = std::max<int64_t>(1 << 20, mneed);
+  (void)maxdeg;
   cv.meas_scr = off; off = align_up(off + cv.meas_scr_cap * 8);
   int mcb = 1;
   for (int col = 0; col < 4; ++col) {
@@ -1131,22 +1137,38 @@ int gauge_bp_t(hpt_sim* s, int init, int* sweeps_out, double* delta_out) {
 
 template <typename T>
 int meas_outgoing(hpt_sim* s, bool only_first_leg) {
-  // jobs for every (site, leg), batched within the scratch and partial budgets
+  // Per site, one read of the pinned slice T_v gives the last leg's outgoing
+  // message and P = T_v contracted with the last leg's incoming message;
+  // the other legs' outgoing messages come from P (float64, 1/chi of the
+  // slice) through the generic contraction jobs.  Sites are batched within
+  // the scratch and partial budgets.
+  std::vector<LastLegJob> ll;
   std::vector<MeasJob> batch;
   int64_t used = 0, pused = 0;
   auto flush = [&]() -> int {
-    if (batch.empty()) return 0;
-    int64_t totals[4];
-    const int64_t pneed = meas_plan(batch.data(), (int)batch.size(), totals);
-    if (pneed > s->cv.part_cap) return HPT_ENOMEM;
-    MeasJob* jd;
-    RC(stage(s, batch.data(), (int)batch.size(), &jd));
-    KR(meas_launch(jd, (int)batch.size(), totals, s->fp32 ? 0 : 1, s->part, s->stream));
+    if (!ll.empty()) {
+      const int64_t blocks = last_leg_plan(ll.data(), (int)ll.size());
+      if (blocks < 0) return HPT_EINVAL;
+      LastLegJob* ld;
+      RC(stage(s, ll.data(), (int)ll.size(), &ld));
+      KR(launch_last_leg(ld, (int)ll.size(), blocks, s->fp32 ? 0 : 1, s->stream));
+    }
+    if (!batch.empty()) {
+      int64_t totals[4];
+      const int64_t pneed = meas_plan(batch.data(), (int)batch.size(), totals);
+      if (pneed > s->cv.part_cap) return HPT_ENOMEM;
+      MeasJob* jd;
+      RC(stage(s, batch.data(), (int)batch.size(), &jd));
+      KR(meas_launch(jd, (int)batch.size(), totals, 1, s->part, s->stream));
+    }
+    ll.clear();
     batch.clear();
     used = 0;
     pused = 0;
     return 0;
   };
+  auto in_msg = [&](const SiteInfo& si, int l) { return mmsg_slot(s, si.bond[l], dir_from(s, si.bond[l], si.nbr[l])); };
+  auto out_msg = [&](const SiteInfo& si, int v, int l) { return mmsg_hat_slot(s, si.bond[l], dir_from(s, si.bond[l], v)); };
   for (int v = 0; v < s->N; ++v) {
     const SiteInfo& si = s->sites[v];
     int64_t dims[5];
@@ -1155,40 +1177,61 @@ int meas_outgoing(hpt_sim* s, bool only_first_leg) {
     for (int l = 0; l < si.deg; ++l) slice *= dims[l];
     const int p = v == s->centre ? 3 : 0;
     const T* Tv = psi_of<T>(s, v) + (int64_t)p * slice;
-    for (int k = 0; k < si.deg; ++k) {
+    const int L = si.deg - 1;
+    const int64_t rows = slice / dims[L];
+    LastLegJob lj;
+    std::memset(&lj, 0, sizeof(lj));
+    lj.T = Tv;
+    lj.rows = rows;
+    lj.nL = (int)dims[L];
+    lj.nx = L;
+    for (int l = 0; l < L; ++l) {
+      lj.xm[l] = in_msg(si, l);
+      lj.xd[l] = (int)dims[l];
+    }
+    lj.mL = in_msg(si, L);
+    lj.out = out_msg(si, v, L);
+    std::vector<MeasJob> js;
+    int64_t need = rows + last_leg_blocks(rows) * dims[L], pjob = 0;
+    for (int k = 0; k < L; ++k) {
       if (only_first_leg && k > 0) break;
       MeasJob j;
       std::memset(&j, 0, sizeof(j));
-      j.T = Tv;
       j.I = 1;
       j.O = 1;
       for (int l = 0; l < k; ++l) {
         j.I *= dims[l];
-        const int b = si.bond[l];
-        j.xm[j.nx] = mmsg_slot(s, b, dir_from(s, b, si.nbr[l]));
+        j.xm[j.nx] = in_msg(si, l);
         j.xd[j.nx++] = (int)dims[l];
       }
-      for (int l = k + 1; l < si.deg; ++l) {
+      for (int l = k + 1; l < L; ++l) {
         j.O *= dims[l];
-        const int b = si.bond[l];
-        j.ym[j.ny] = mmsg_slot(s, b, dir_from(s, b, si.nbr[l]));
+        j.ym[j.ny] = in_msg(si, l);
         j.yd[j.ny++] = (int)dims[l];
       }
       j.nk = dims[k];
-      const int bk = si.bond[k];
-      j.out = mmsg_hat_slot(s, bk, dir_from(s, bk, v));
-      const int64_t need = j.I + j.O + (j.O > 1 ? j.I * j.nk : 0);
-      const int64_t pjob = (j.O > 1 ? ceil_div(j.O, 256) * j.I * j.nk : 0) + ceil_div(j.I, 64 * 256) * j.nk;
-      if (need > s->cv.meas_scr_cap || pjob > s->cv.part_cap) return HPT_ENOMEM;
-      if (used + need > s->cv.meas_scr_cap || pused + pjob > s->cv.part_cap || batch.size() >= 4096)
-        RC(flush());
+      j.out = out_msg(si, v, k);
+      need += j.I + j.O + (j.O > 1 ? j.I * j.nk : 0);
+      pjob += (j.O > 1 ? ceil_div(j.O, 256) * j.I * j.nk : 0) + ceil_div(j.I, 64 * 256) * j.nk;
+      js.push_back(j);
+    }
+    if (need > s->cv.meas_scr_cap || pjob > s->cv.part_cap) return HPT_ENOMEM;
+    if (used + need > s->cv.meas_scr_cap || pused + pjob > s->cv.part_cap || ll.size() >= 1024 ||
+        batch.size() + js.size() > 4096)
+      RC(flush());
+    lj.P = s->meas_scr + used;
+    lj.part = lj.P + rows;
+    used += rows + last_leg_blocks(rows) * dims[L];
+    ll.push_back(lj);
+    for (MeasJob& j : js) {
+      j.T = lj.P;
       j.x = s->meas_scr + used;
       j.y = j.x + j.I;
       j.S = j.y + j.O;
-      used += need;
-      pused += pjob;
+      used += j.I + j.O + (j.O > 1 ? j.I * j.nk : 0);
       batch.push_back(j);
     }
+    pused += pjob;
   }
   return flush();
 }

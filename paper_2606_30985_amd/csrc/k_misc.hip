@@ -264,6 +264,92 @@ __global__ void meas_gemv_t_reduce(const MeasJob* jobs, const double* part) {
   }
 }
 
+constexpr int LL_ROWS = 1024;   // rows per block: 4 waves x 64 lanes x 4 rows
+constexpr int LL_MAXL = 1024;
+
+__device__ inline int find_ll(const LastLegJob* jobs, int njobs, int64_t b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].b0 <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// each lane owns 4 rows (stride 256); for every column e the lane's rows are
+// read once (coalesced along r), folded into P and into the wave's partial of
+// out[e]
+template <typename T>
+__global__ __launch_bounds__(256) void last_leg_kernel(const LastLegJob* jobs, int njobs) {
+  const LastLegJob& job = jobs[find_ll(jobs, njobs, blockIdx.x)];
+  const int64_t blk = blockIdx.x - job.b0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double wp[4][LL_MAXL];
+  const int64_t rows = job.rows;
+  const int nL = job.nL;
+  const T* Tp = (const T*)job.T;
+  double xr[4], pacc[4];
+  int64_t rr[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t r = blk * LL_ROWS + q * 256 + threadIdx.x;
+    rr[q] = r;
+    pacc[q] = 0.0;
+    double v = 0.0;
+    if (r < rows) {
+      v = 1.0;
+      int64_t rem = r;
+      for (int l = 0; l < job.nx; ++l) {
+        v *= job.xm[l][rem % job.xd[l]];
+        rem /= job.xd[l];
+      }
+    }
+    xr[q] = v;
+  }
+  for (int e = 0; e < nL; ++e) {
+    const double me = job.mL[e];
+    const T* col = Tp + rows * e;
+    double sacc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (rr[q] < rows) {
+        const double t = (double)col[rr[q]];
+        pacc[q] += t * me;
+        sacc += t * xr[q];
+      }
+    }
+    sacc = wave_sum(sacc);
+    if (lane == 0) wp[wave][e] = sacc;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (rr[q] < rows) job.P[rr[q]] = pacc[q];
+  __syncthreads();
+  for (int e = threadIdx.x; e < nL; e += blockDim.x)
+    job.part[blk * nL + e] = (wp[0][e] + wp[1][e]) + (wp[2][e] + wp[3][e]);
+}
+
+// out[e] = sum over blocks of part[blk, e]: 8 groups of 128 columns, fixed order
+__global__ __launch_bounds__(1024) void last_leg_reduce(const LastLegJob* jobs) {
+  const LastLegJob& job = jobs[blockIdx.x];
+  __shared__ double red[8][129];
+  const int c = threadIdx.x & 127, g = threadIdx.x >> 7;
+  for (int e0 = 0; e0 < job.nL; e0 += 128) {
+    const int e = e0 + c;
+    double acc = 0.0;
+    if (e < job.nL)
+      for (int64_t b = g; b < job.nblk; b += 8) acc += job.part[b * job.nL + e];
+    red[g][c] = acc;
+    __syncthreads();
+    if (g == 0 && e < job.nL) {
+      double s = 0.0;
+      for (int q = 0; q < 8; ++q) s += red[q][c];
+      job.out[e] = s;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(256) void meas_norm_kernel(const MeasNormJob* jobs, double alpha,
                                                         double* delta) {
   const MeasNormJob job = jobs[blockIdx.x];
@@ -416,6 +502,32 @@ int launch_log_product(const double* x, int n_num, int n_den, const double* delt
   hipLaunchKernelGGL(log_product_kernel, dim3(1), dim3(256), 0, s, x, n_num, n_den, delta,
                      n_delta, res);
   HPT_LAUNCH_CHECK("log_product_kernel");
+  return 0;
+}
+
+int64_t last_leg_blocks(int64_t rows) { return ceil_div(rows, LL_ROWS); }
+
+int64_t last_leg_plan(LastLegJob* jobs, int njobs) {
+  int64_t b = 0;
+  for (int j = 0; j < njobs; ++j) {
+    if (jobs[j].nL < 1 || jobs[j].nL > LL_MAXL || jobs[j].rows < 1) return -1;
+    jobs[j].b0 = b;
+    jobs[j].nblk = ceil_div(jobs[j].rows, LL_ROWS);
+    b += jobs[j].nblk;
+  }
+  return b > 0x7fffffffll ? -1 : b;
+}
+
+int launch_last_leg(const LastLegJob* jobs_dev, int njobs, int64_t blocks, int is_double, hipStream_t s) {
+  if (njobs <= 0) return 0;
+  if (blocks < 1 || blocks > 0x7fffffffll) return -1;
+  if (is_double)
+    hipLaunchKernelGGL(last_leg_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, jobs_dev, njobs);
+  else
+    hipLaunchKernelGGL(last_leg_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, jobs_dev, njobs);
+  HPT_LAUNCH_CHECK("last_leg_kernel");
+  hipLaunchKernelGGL(last_leg_reduce, dim3(njobs), dim3(1024), 0, s, jobs_dev);
+  HPT_LAUNCH_CHECK("last_leg_reduce");
   return 0;
 }
 

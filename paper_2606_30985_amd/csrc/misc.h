@@ -71,6 +71,28 @@ int64_t meas_plan(MeasJob* jobs_host, int njobs, int64_t totals[4]);
 int meas_launch(const MeasJob* jobs_dev, int njobs, const int64_t totals[4], int is_double,
                 double* part, hipStream_t s);
 
+// One pass over a pinned slice T (rows x nL, column-major, last leg slowest):
+// P[r] = sum_e T[r, e] mL[e] (T contracted with the last leg's message, for
+// the other legs' outgoing messages) and out[e] = sum_r T[r, e] x[r] with
+// x[r] = prod_l xm[l][r_l] over the other legs (the last leg's outgoing
+// message).  Block partials of out go to part (nblk x nL), summed in a fixed
+// order by a second kernel.  nL <= 1024.
+struct LastLegJob {
+  const void* T; int64_t rows; int nL;
+  int nx; const double* xm[3]; int xd[3];   // messages of the other legs, first leg fastest
+  const double* mL;    // nL
+  double* P;           // rows
+  double* part;        // nblk x nL
+  double* out;         // nL
+  int64_t nblk, b0;    // blocks of this job, first block in the launch (set by the launcher)
+};
+// blocks (rows of the partial buffer) a job of `rows` rows needs
+int64_t last_leg_blocks(int64_t rows);
+// fills b0 / nblk of the host jobs; returns the launch's block count, -1 if
+// a job is out of range (nL > 1024)
+int64_t last_leg_plan(LastLegJob* jobs_host, int njobs);
+int launch_last_leg(const LastLegJob* jobs_dev, int njobs, int64_t blocks, int is_double, hipStream_t s);
+
 // normalise, sign continuity, damp, normalise; delta[i] = max |mn - mo|
 struct MeasNormJob {
   double* mo;
