@@ -202,11 +202,11 @@ __global__ __launch_bounds__(256) void gemm_pipe_kernel(GemmDesc<T> d, int tiles
 // into registers while the MFMAs of the current one run.  The factor goes
 // first into the MFMA, so result blocks are dst^T and the stores of 16 lanes
 // run along a.
-template <int NP>
+template <int NP, int KS>
 __global__ __launch_bounds__(256) void mode_product_kernel(const float* __restrict__ src, float* __restrict__ dst,
                                                            const float* __restrict__ S, int n, int64_t inner,
                                                            int64_t Z, int64_t strips_per_z) {
-  constexpr int NB = NP / 16, KS = NP / 4;
+  constexpr int NB = NP / 16;   // KS = ceil(n / 4) k-steps of 4 (<= NP / 4)
   constexpr int SP = NP + ((NP % 32) == 0 ? 16 : 0);   // row stride = 16 mod 32
   __shared__ float Sl[NP * SP];                         // Sl[k * SP + j] = S[j, k]
   for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
@@ -393,12 +393,21 @@ __global__ __launch_bounds__(256) void leg_gram_kernel(const float* __restrict__
     }
     return v;
   };
+  f4 xa[HB], yb[HB], xn[HB], yn[HB];
+  if (c0 < c1) {
+#pragma unroll
+    for (int x = 0; x < HB; ++x) xa[x] = load(psi, c0, (ib0 + x) * 16 + r16);
+#pragma unroll
+    for (int y = 0; y < HB; ++y) yb[y] = load(cur, c0, (jb0 + y) * 16 + r16);
+  }
   for (int64_t c = c0; c < c1; ++c) {
-    f4 xa[HB], yb[HB];
+    // the next chunk's operands are in flight during this chunk's MFMAs
+    if (c + 1 < c1) {
 #pragma unroll
-    for (int x = 0; x < HB; ++x) xa[x] = load(psi, c, (ib0 + x) * 16 + r16);
+      for (int x = 0; x < HB; ++x) xn[x] = load(psi, c + 1, (ib0 + x) * 16 + r16);
 #pragma unroll
-    for (int y = 0; y < HB; ++y) yb[y] = load(cur, c, (jb0 + y) * 16 + r16);
+      for (int y = 0; y < HB; ++y) yn[y] = load(cur, c + 1, (jb0 + y) * 16 + r16);
+    }
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -411,6 +420,106 @@ __global__ __launch_bounds__(256) void leg_gram_kernel(const float* __restrict__
           acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(yb[y][t], xa[x][t], acc[x][y], 0, 0, 0);
         }
       }
+#pragma unroll
+    for (int x = 0; x < HB; ++x) xa[x] = xn[x];
+#pragma unroll
+    for (int y = 0; y < HB; ++y) yb[y] = yn[y];
+  }
+  // block (x, y), register e: out[16 (ib0 + x) + r16, 16 (jb0 + y) + 4 kq + e]
+  double* out = part + (int64_t)blockIdx.x * n * n;
+#pragma unroll
+  for (int x = 0; x < HB; ++x)
+#pragma unroll
+    for (int y = 0; y < HB; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = (ib0 + x) * 16 + r16, j = (jb0 + y) * 16 + 4 * kq + e;
+        if (ib0 + x < NB && jb0 + y < NB && i < n && j < n) out[(int64_t)j * n + i] = (double)acc[x][y][e];
+      }
+}
+
+// Leg Gram of the float32 form for inner > 1, inner % 4 == 0: the reduction
+// index k = a + inner r is flattened over (a, r); chunks of 32 consecutive k
+// of all n columns of both operands are fetched with 16-byte loads (8 lanes
+// cover 128 contiguous bytes of one column), staged in LDS as [k][column],
+// and fed to the MFMAs (four waves, 2 x 2 quadrants of 16 x 16 blocks of the
+// padded n x n result).  The next chunk is fetched during this chunk's MFMAs.
+template <int NP>
+__global__ __launch_bounds__(256) void leg_gram_lds_kernel(const float* __restrict__ psi, const float* __restrict__ cur,
+                                                           int n, uint32_t inner, uint32_t ktotal,
+                                                           uint32_t chunks_per_wg, double* __restrict__ part) {
+  constexpr int NB = NP / 16, HB = (NB + 1) / 2;
+  constexpr int KC = 32;
+  constexpr int SP = NP + 4;
+  constexpr int PASSES = (NP + 31) / 32;
+  __shared__ float As[KC * SP];   // As[k * SP + col]
+  __shared__ float Bs[KC * SP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r16 = lane & 15, kq = lane >> 4;
+  const int ib0 = (wave >> 1) * HB, jb0 = (wave & 1) * HB;
+  const int kg = tid & 7, cl = tid >> 3;
+  f4 ra[PASSES], rb[PASSES];
+  auto gload = [&](uint32_t c) {
+    const uint32_t k = c * KC + 4 * kg;
+    const bool kok = k < ktotal;
+    const uint32_t r = kok ? k / inner : 0u;
+    const uint32_t a = kok ? k - r * inner : 0u;
+    const uint64_t base = (uint64_t)a + (uint64_t)inner * ((uint64_t)n * r);
+#pragma unroll
+    for (int q = 0; q < PASSES; ++q) {
+      const int col = cl + 32 * q;
+      f4 x{0.f, 0.f, 0.f, 0.f}, y{0.f, 0.f, 0.f, 0.f};
+      if (kok && col < n) {
+        const uint64_t off = base + (uint64_t)inner * col;
+        x = *(const f4*)(psi + off);
+        y = *(const f4*)(cur + off);
+      }
+      ra[q] = x;
+      rb[q] = y;
+    }
+  };
+  f4 acc[HB][HB];
+#pragma unroll
+  for (int x = 0; x < HB; ++x)
+#pragma unroll
+    for (int y = 0; y < HB; ++y) acc[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+  const uint32_t nchunks = (ktotal + KC - 1) / KC;
+  const uint32_t c0 = blockIdx.x * chunks_per_wg;
+  const uint32_t c1 = c0 + chunks_per_wg < nchunks ? c0 + chunks_per_wg : nchunks;
+  if (c0 < c1) gload(c0);
+  for (uint32_t c = c0; c < c1; ++c) {
+    __syncthreads();   // the previous chunk's LDS reads are done
+#pragma unroll
+    for (int q = 0; q < PASSES; ++q) {
+      const int col = cl + 32 * q;
+      if (col < NP) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          As[(4 * kg + t) * SP + col] = ra[q][t];
+          Bs[(4 * kg + t) * SP + col] = rb[q][t];
+        }
+      }
+    }
+    __syncthreads();
+    if (c + 1 < c1) gload(c + 1);
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int kr = 4 * ks + kq;
+      float xa[HB], yb[HB];
+#pragma unroll
+      for (int x = 0; x < HB; ++x) xa[x] = (ib0 + x < NB) ? As[kr * SP + (ib0 + x) * 16 + r16] : 0.f;
+#pragma unroll
+      for (int y = 0; y < HB; ++y) yb[y] = (jb0 + y < NB) ? Bs[kr * SP + (jb0 + y) * 16 + r16] : 0.f;
+#pragma unroll
+      for (int x = 0; x < HB; ++x) {
+        if (ib0 + x >= NB) continue;
+#pragma unroll
+        for (int y = 0; y < HB; ++y) {
+          if (jb0 + y >= NB) continue;
+          // cur first: the block is out^T, so lanes run along i
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(yb[y], xa[x], acc[x][y], 0, 0, 0);
+        }
+      }
+    }
   }
   // block (x, y), register e: out[16 (ib0 + x) + r16, 16 (jb0 + y) + 4 kq + e]
   double* out = part + (int64_t)blockIdx.x * n * n;
@@ -605,7 +714,7 @@ int resident_grid(const void* kernel, int threads, int64_t work_waves) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * per_cu));
 }
 
-template <int NP>
+template <int NP, int KS = NP / 4>
 int launch_mode(const float* src, float* dst, const float* S, int n, int64_t inner, int64_t outer, hipStream_t s) {
   if (inner == 1) {
     const int64_t strips = ceil_div(outer, 16);
@@ -618,8 +727,8 @@ int launch_mode(const float* src, float* dst, const float* S, int n, int64_t inn
     }
   } else {
     const int64_t spz = ceil_div(inner, 16);
-    const int g = resident_grid((const void*)mode_product_kernel<NP>, 256, spz * outer);
-    hipLaunchKernelGGL((mode_product_kernel<NP>), dim3(g), dim3(256), 0, s, src, dst, S, n, inner, outer, spz);
+    const int g = resident_grid((const void*)mode_product_kernel<NP, KS>, 256, spz * outer);
+    hipLaunchKernelGGL((mode_product_kernel<NP, KS>), dim3(g), dim3(256), 0, s, src, dst, S, n, inner, outer, spz);
   }
   HPT_LAUNCH_CHECK("mode_product_kernel");
   return 0;
@@ -627,6 +736,17 @@ int launch_mode(const float* src, float* dst, const float* S, int n, int64_t inn
 template <int NP>
 int launch_leg_gram(const float* psi, const float* cur, int n, int64_t inner, int64_t outer, int64_t chunks_per_r,
                     int64_t cpw, int G, double* part, hipStream_t s) {
+  if (inner > 1 && inner % 4 == 0 && inner * outer < ((int64_t)1 << 31)) {
+    // flattened reduction index, chunks of 32
+    const int64_t ktotal = inner * outer;
+    const int64_t nch = ceil_div(ktotal, 32);
+    const int64_t cw = ceil_div(nch, G);
+    const int g2 = (int)ceil_div(nch, cw);
+    hipLaunchKernelGGL((leg_gram_lds_kernel<NP>), dim3(g2), dim3(256), 0, s, psi, cur, n, (uint32_t)inner,
+                       (uint32_t)ktotal, (uint32_t)cw, part);
+    HPT_LAUNCH_CHECK("leg_gram_lds_kernel");
+    return g2;
+  }
   if (inner == 1)
     hipLaunchKernelGGL((leg_gram_kernel<NP, true, false>), dim3(G), dim3(256), 0, s, psi, cur, n, inner, outer,
                        chunks_per_r, cpw, part);
@@ -637,7 +757,7 @@ int launch_leg_gram(const float* psi, const float* cur, int n, int64_t inner, in
     hipLaunchKernelGGL((leg_gram_kernel<NP, false, false>), dim3(G), dim3(256), 0, s, psi, cur, n, inner, outer,
                        chunks_per_r, cpw, part);
   HPT_LAUNCH_CHECK("leg_gram_kernel");
-  return 0;
+  return G;
 }
 }  // namespace
 
@@ -664,7 +784,8 @@ int leg_gram_f32(const float* psi, const float* cur, int n, int64_t inner, int64
     case 7: r = launch_leg_gram<112>(psi, cur, n, inner, outer, chunks_per_r, cpw, (int)G, part, s); break;
     default: r = launch_leg_gram<128>(psi, cur, n, inner, outer, chunks_per_r, cpw, (int)G, part, s); break;
   }
-  if (r) return r;
+  if (r < 0) return r;
+  const int parts = r;   // workgroups that wrote a partial
   {
     const double el = (double)inner * n * outer;
     RC_PROF(prof_end(s, 3, 2.0 * el * n, 4.0 * 2.0 * el + 8.0 * n2));
@@ -673,7 +794,7 @@ int leg_gram_f32(const float* psi, const float* cur, int n, int64_t inner, int64
   d.M = n; d.N = n; d.K = 1; d.R = 1; d.Z = 1;
   d.C = out; d.ldc = n; d.c_double = 1; d.alpha = 1.0; d.beta = 0.0;
   const int64_t blocks = ceil_div(n2, 64);
-  hipLaunchKernelGGL(gemm_reduce_kernel<float>, dim3((unsigned)blocks), dim3(1024), 0, s, d, (int)G, (const double*)part);
+  hipLaunchKernelGGL(gemm_reduce_kernel<float>, dim3((unsigned)blocks), dim3(1024), 0, s, d, parts, (const double*)part);
   HPT_LAUNCH_CHECK("gemm_reduce_kernel");
   return 1;
 }
@@ -693,7 +814,10 @@ int mode_product_f32(const float* S, const float* src, float* dst, int n, int64_
     case 4: r = launch_mode<64>(src, dst, S, n, inner, outer, s); break;
     case 5: r = launch_mode<80>(src, dst, S, n, inner, outer, s); break;
     case 6: r = launch_mode<96>(src, dst, S, n, inner, outer, s); break;
-    case 7: r = launch_mode<112>(src, dst, S, n, inner, outer, s); break;
+    case 7:
+      // n in (96, 100] (chi_max = 100) needs 25 k-steps, not 28
+      r = n <= 100 ? launch_mode<112, 25>(src, dst, S, n, inner, outer, s) : launch_mode<112>(src, dst, S, n, inner, outer, s);
+      break;
     default: r = launch_mode<128>(src, dst, S, n, inner, outer, s); break;
   }
   if (r) return r;
