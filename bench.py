@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--bp-init", default="warm", choices=["warm", "uniform"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trace", default="", help="append per-step records (JSON lines) to this file")
+    ap.add_argument("--profile-all", action="store_true",
+                    help="kernel event profile over every layer (warm-up included), for counter comparisons")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="first copy this many bytes with the library's plain copy kernel (counter calibration)")
     return ap.parse_args()
 
 
@@ -89,6 +93,28 @@ def cpu_baseline(chi, L, dt, sample_chi=30):
             "bond_updates_per_s_extrapolated": 1.0 / est}
 
 
+def traffic_ratio(kernel_key):
+    """HBM bytes per algorithmic byte of a kernel family, from the committed
+    PMC summary; None when the kernel source has changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "mode_product_kernel_10x10_chi100_pmc.md")
+    if kernel_key != "mode" or not os.path.exists(path):
+        return None
+    ratio = sha = src = None
+    for line in open(path):
+        f = line.split()
+        if len(f) == 3 and f[0] == "traffic_ratio" and f[1] == "mode_product_kernel":
+            ratio = float(f[2])
+        if len(f) == 3 and f[0] == "kernel_source_sha256":
+            src, sha = f[1], f[2]
+    if ratio is None or sha is None:
+        return None
+    with open(os.path.join(ROOT, src), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != sha:
+            return None
+    return ratio
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -97,6 +123,16 @@ def main():
         sys.exit(2)
     import torch
     from paper_2606_30985_amd import hpt
+
+    if args.calibrate_copy:
+        # one plain copy of known size through permute_generic (identity permutation)
+        nel = args.calibrate_copy // 4
+        src = torch.rand(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        hpt.permute(src, dst, [0])
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"# calibration copy: {nel * 4} bytes read, {nel * 4} bytes written", file=sys.stderr, flush=True)
 
     L, chi = args.L, args.chi
     sim = hpt.Simulator(Lx=L, Ly=L, chi_max=chi, dt=args.dt, J=1.0, h=1.0, precision=args.precision,
@@ -117,10 +153,13 @@ def main():
             trace.flush()
         return rec
 
+    if args.profile_all:
+        hpt.profile_gemm(True)
     for _ in range(args.warmup):
         one(False)
     torch.cuda.synchronize()
-    hpt.profile_gemm(True)
+    if not args.profile_all:
+        hpt.profile_gemm(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     recs = [one(True) for _ in range(args.steps)]
@@ -133,6 +172,7 @@ def main():
     prof = kinds[dom]
     n_bonds = (L - 1) * L * 2
     value = args.steps / elapsed
+    ratio = traffic_ratio(dom)
     achieved = prof["flops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else 0.0
     # float64 products (the Gram of float32 data, or every product of the
     # float64 form) run on the FP64 MFMA
@@ -162,12 +202,18 @@ def main():
                    "C": [r["C"] for r in recs]},
         "roofline": {"bound": "mfma", "kernel": KERNEL_NAMES[dom],
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "launches": prof["launches"], "kernel_ms": prof["ms"],
+                     # HBM bytes per launch: PMC FETCH_SIZE + WRITE_SIZE (copy-calibrated) per
+                     # algorithmic byte, times this run's algorithmic bytes per launch
+                     "traffic": (None if ratio is None else ratio * prof["bytes"] / max(prof["launches"], 1)),
+                     "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes_per_launch": prof["bytes"] / max(prof["launches"], 1),
+                     "launches": prof["launches"], "kernel_ms": prof["ms"],
                      "avg_launch_ms": prof["ms"] / max(prof["launches"], 1),
                      "flop_per_launch": prof["flops"] / max(prof["launches"], 1),
                      "kernel_share_of_step": prof["ms"] * 1e-3 / elapsed,
                      "contractions": {KERNEL_NAMES[k]: {"launches": v["launches"], "ms": v["ms"],
-                                                        "tflops": v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else 0.0}
+                                                        "tflops": v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else 0.0,
+                                                        "algorithmic_bytes": v["bytes"]}
                                       for k, v in kinds.items()}},
     }
     if not args.no_cpu_baseline:

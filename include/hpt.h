@@ -70,6 +70,8 @@ extern "C" {
 #define HPT_FLAG_PINV_CUT               (1u << 5)  /* an environment eigenvalue was dropped */
 #define HPT_FLAG_BETHE_ZERO             (1u << 6)  /* some vs_v or Z_e was exactly zero */
 #define HPT_FLAG_QR_FALLBACK            (1u << 7)  /* CholeskyQR2 failed, Householder used */
+#define HPT_FLAG_TRAP_REMEDIATED        (1u << 9)  /* a verified trap was retried, the retry stands */
+#define HPT_FLAG_TRAP_UNRESOLVED        (1u << 10) /* a verified trap was retried without success */
 #define HPT_FLAG_QR_RANK_DEFICIENT      (1u << 8)  /* a QR block had numerically dependent columns
                                                       (deflated by the pivoted Cholesky) */
 
@@ -98,8 +100,20 @@ typedef struct {
   double  qr_rank_tol;     /* CholeskyQR2 deflates a column when its remaining pivot is
                               <= qr_rank_tol * max diag of the Gram matrix; 0: never
                               deflate (a dependent column sends the block to Householder);
-                              < 0 (default): 0 in the FP64 form, 1e-12 in the FP32 form */
-  int32_t reserved[6];
+                              < 0 (default): 0 in the FP64 form, 1e-14 in the FP32 form */
+  int32_t trap_retry;      /* 1: remediate verified traps (Sec. "BP Fixed-Point Multiplicity",
+                              trap remediation): when a BP of the layer needed >= trap_sweeps
+                              sweeps to converge and C(t) fell below half of the previous
+                              layer's value while the gate error grew less than twofold, the
+                              measurement BP is rerun from a uniform start with trap_alpha;
+                              the retry stands when it converges and is no such drop
+                              (HPT_FLAG_TRAP_REMEDIATED), else HPT_FLAG_TRAP_UNRESOLVED.
+                              The previous layer is the last hpt_measure at an earlier step.
+                              0 (default): off */
+  int32_t reserved0;
+  double  trap_alpha;      /* damping of the retry; <= 0 (default): 0.5 when the measurement
+                              damping is >= 1, else 0.8 */
+  int32_t reserved[4];
 } hpt_config;
 
 typedef struct {

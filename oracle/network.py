@@ -54,6 +54,9 @@ FLAG_DEGENERATE_CUT = 1 << 4
 FLAG_PINV_CUT = 1 << 5
 FLAG_BETHE_ZERO = 1 << 6
 FLAG_QR_FALLBACK = 1 << 7
+FLAG_QR_RANK_DEFICIENT = 1 << 8
+FLAG_TRAP_REMEDIATED = 1 << 9
+FLAG_TRAP_UNRESOLVED = 1 << 10
 
 
 @dataclass
@@ -75,6 +78,9 @@ class Config:
     meas_tol: Optional[float] = None      # None -> bp_tol
     meas_max_sweeps: Optional[int] = None
     gauge_bp: bool = True
+    trap_sweeps: int = 30                 # trap-candidate threshold (sweeps)
+    trap_retry: bool = False              # remediate verified traps (run.remediate_trap)
+    trap_alpha: Optional[float] = None    # damping of the retry; None -> paper's rule
 
 
 # --------------------------------------------------------------------------
@@ -329,9 +335,10 @@ class OperatorNetwork:
             out.append(self.psi[v][..., p])
         return out
 
-    def measure(self):
+    def measure(self, alpha=None):
         cfg, lat = self.cfg, self.lat
-        alpha = cfg.bp_alpha if cfg.meas_alpha is None else cfg.meas_alpha
+        if alpha is None:
+            alpha = cfg.bp_alpha if cfg.meas_alpha is None else cfg.meas_alpha
         tol = cfg.bp_tol if cfg.meas_tol is None else cfg.meas_tol
         maxs = cfg.bp_max_sweeps if cfg.meas_max_sweeps is None else cfg.meas_max_sweeps
         T = self.pinned()
@@ -373,7 +380,7 @@ class OperatorNetwork:
         flags = 0
         if delta >= tol:
             flags |= FLAG_BP_NOT_CONVERGED_MEAS
-        if sweeps >= 30 and delta < tol:
+        if sweeps >= cfg.trap_sweeps and delta < tol:
             flags |= FLAG_TRAP_CANDIDATE
         vs = [contract_all(T[v], incoming_vecs(v, m)) for v in range(lat.n_sites)]
         Ze = [float(np.dot(m[b][0], m[b][1])) for b in range(lat.n_bonds)]

@@ -127,4 +127,7 @@ struct hpt_sim {
   int gauge_sweeps;
   double gauge_delta;
   double bethe_norm;
+  // last measurement (step, C, gate error) and the one of the layer before
+  int rec_step, prv_step;
+  double rec_C, rec_gate_err, prv_C, prv_gate_err;
 };

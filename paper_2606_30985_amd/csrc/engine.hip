@@ -88,6 +88,8 @@ int validate(const hpt_config* c) {
   if (!(c->bp_alpha > 0.0 && c->bp_alpha <= 1.0) || !(c->bp_tol > 0.0) || c->bp_max_sweeps < 1) return HPT_EINVAL;
   if (c->meas_alpha > 1.0) return HPT_EINVAL;
   if (!(c->qr_rank_tol < 1.0)) return HPT_EINVAL;
+  if (c->trap_retry != 0 && c->trap_retry != 1) return HPT_EINVAL;
+  if (c->trap_alpha > 1.0 || c->trap_sweeps < 1) return HPT_EINVAL;
   if (c->bp_init != HPT_BP_UNIFORM && c->bp_init != HPT_BP_WARM) return HPT_EINVAL;
   // the storage of one interior site must stay addressable with 64-bit offsets
   // and its element count below 2^40
@@ -921,7 +923,7 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
         j = SmallGemmJob{q1, q0, K, nullptr, nullptr, nullptr, bc.Tm[1], ldR, 0, bc.Tm[0], ldR, 1, bc.G, ldR, 1.0, 0.0, nullptr};
       gj.push_back(j);
       sj.push_back(SvdJob{bc.G, ldR, std::max(q0, q1), std::min(q0, q1), bc.V, ldR, bc.s, bc.perm, nullptr,
-                          s->slots[q].svd_state});
+                          s->slots[q].svd_state, (double*)(s->slots[q].svd_state + 8)});
     }
     SmallGemmJob* gd;
     RC(stage(s, gj.data(), nb, &gd));
@@ -932,7 +934,8 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
     int nmax = 0;
     for (auto& j : sj) nmax = std::max(nmax, j.n);
     if (nmax > 64)
-      KR(launch_block_jacobi_svd(sd, sj.data(), nb, s->stream));
+      KR(launch_block_jacobi_svd(sd, sj.data(), nb, s->stream, (int*)(s->res + 12),
+                                 (volatile int*)(s->hscratch + s->hscratch_bytes - 64)));
     else
       KR(launch_jacobi_svd(sd, nb, s->stream));
   }
@@ -1236,8 +1239,17 @@ int meas_outgoing(hpt_sim* s, bool only_first_leg) {
   return flush();
 }
 
+// One measurement BP (fresh uniform start, damping alpha) and the Bethe sum.
+struct MeasResult {
+  double C, logC;
+  int sign;
+  int sweeps;
+  double delta;
+  uint32_t flags;   // BETHE_ZERO only
+};
+
 template <typename T>
-int measure_t(hpt_sim* s, hpt_measurement* out) {
+int meas_bp_t(hpt_sim* s, double alpha, MeasResult& mr) {
   const int nbd = 2 * s->nb;
   for (int b = 0; b < s->nb; ++b)
     for (int d = 0; d < 2; ++d)
@@ -1245,7 +1257,6 @@ int measure_t(hpt_sim* s, hpt_measurement* out) {
   std::vector<MeasNormJob> nj(nbd);
   for (int b = 0; b < s->nb; ++b)
     for (int d = 0; d < 2; ++d) nj[2 * b + d] = MeasNormJob{mmsg_slot(s, b, d), mmsg_hat_slot(s, b, d), s->chi[b]};
-  const double alpha = s->cfg.meas_alpha > 0.0 ? s->cfg.meas_alpha : s->cfg.bp_alpha;
   const double tol = s->cfg.meas_tol > 0.0 ? s->cfg.meas_tol : s->cfg.bp_tol;
   const int maxs = s->cfg.meas_max_sweeps > 0 ? s->cfg.meas_max_sweeps : s->cfg.bp_max_sweeps;
   int sweeps = 0;
@@ -1281,16 +1292,55 @@ int measure_t(hpt_sim* s, hpt_measurement* out) {
   HPT_HIP(hipMemcpyAsync(s->hscratch, s->res, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   RC(sync_stream(s));
   std::memcpy(res, s->hscratch, sizeof(res));
-  uint32_t flags = s->layer_flags;
-  double C, logC;
-  int sign;
+  mr.flags = 0;
   if (res[2] != 0.0) {
-    C = 0.0; logC = -INFINITY; sign = 0; flags |= HPT_FLAG_BETHE_ZERO;
+    mr.C = 0.0; mr.logC = -INFINITY; mr.sign = 0; mr.flags |= HPT_FLAG_BETHE_ZERO;
   } else if (res[3] != 0.0) {
-    C = NAN; logC = NAN; sign = 0; flags |= HPT_FLAG_BETHE_ZERO;
+    mr.C = NAN; mr.logC = NAN; mr.sign = 0; mr.flags |= HPT_FLAG_BETHE_ZERO;
   } else {
-    logC = res[0]; sign = res[1] < 0 ? -1 : 1; C = sign * std::exp(logC);
+    mr.logC = res[0]; mr.sign = res[1] < 0 ? -1 : 1; mr.C = mr.sign * std::exp(mr.logC);
   }
+  mr.sweeps = sweeps;
+  mr.delta = delta;
+  return 0;
+}
+
+template <typename T>
+int measure_t(hpt_sim* s, hpt_measurement* out) {
+  const double alpha = s->cfg.meas_alpha > 0.0 ? s->cfg.meas_alpha : s->cfg.bp_alpha;
+  const double tol = s->cfg.meas_tol > 0.0 ? s->cfg.meas_tol : s->cfg.bp_tol;
+  // the previous layer's measurement (for the trap rule)
+  if (s->rec_step >= 0 && s->rec_step < s->step) {
+    s->prv_step = s->rec_step;
+    s->prv_C = s->rec_C;
+    s->prv_gate_err = s->rec_gate_err;
+  }
+  MeasResult mr;
+  RC(meas_bp_t<T>(s, alpha, mr));
+  uint32_t flags = s->layer_flags | mr.flags;
+  if (mr.sweeps >= s->cfg.trap_sweeps && mr.delta < tol) flags |= HPT_FLAG_TRAP_CANDIDATE;
+  // trap remediation (Sec. "BP Fixed-Point Multiplicity"): a candidate whose
+  // C(t) fell below half of the previous layer's while the gate error grew
+  // less than twofold is retried with the other damping; the retry stands
+  // when it converges and is no longer such a drop
+  if (s->cfg.trap_retry && s->prv_step >= 0 && s->prv_step < s->step && (flags & HPT_FLAG_TRAP_CANDIDATE) &&
+      std::fabs(mr.C) < 0.5 * std::fabs(s->prv_C) &&
+      (s->layer_gate_err < 2.0 * s->prv_gate_err || s->layer_gate_err == 0.0)) {
+    const double alt = s->cfg.trap_alpha > 0.0 ? s->cfg.trap_alpha : (alpha >= 1.0 ? 0.5 : 0.8);
+    MeasResult r2;
+    RC(meas_bp_t<T>(s, alt, r2));
+    if (r2.delta < tol && std::fabs(r2.C) >= 0.5 * std::fabs(s->prv_C)) {
+      mr = r2;
+      flags = (flags & ~HPT_FLAG_BETHE_ZERO) | r2.flags | HPT_FLAG_TRAP_REMEDIATED;
+    } else {
+      flags |= HPT_FLAG_TRAP_UNRESOLVED;
+    }
+  }
+  const double C = mr.C, logC = mr.logC, delta = mr.delta;
+  const int sign = mr.sign, sweeps = mr.sweeps;
+  s->rec_step = s->step;
+  s->rec_C = C;
+  s->rec_gate_err = s->layer_gate_err;
   if (delta >= tol) flags |= HPT_FLAG_BP_NOT_CONVERGED_MEAS;
   if (sweeps >= s->cfg.trap_sweeps && delta < tol) flags |= HPT_FLAG_TRAP_CANDIDATE;
   if (s->bethe_norm == s->bethe_norm && s->bethe_norm >= 2.0) flags |= HPT_FLAG_NORM_EXPLODED;
@@ -1372,6 +1422,8 @@ void make_gate_tables(hpt_sim* s) {
 
 template <typename T>
 int reset_t(hpt_sim* s) {
+  s->rec_step = s->prv_step = -1;
+  s->rec_C = s->prv_C = s->rec_gate_err = s->prv_gate_err = 0.0;
   for (int b = 0; b < s->nb; ++b) {
     s->chi[b] = 1;
     s->lam[b].assign(1, 1.0);
@@ -1425,6 +1477,8 @@ int hpt_config_default(hpt_config* c) {
   c->gauge_bp = 1;
   c->trap_sweeps = 30;
   c->qr_rank_tol = -1.0;
+  c->trap_retry = 0;
+  c->trap_alpha = -1.0;
   return HPT_OK;
 }
 
@@ -1544,7 +1598,7 @@ int hpt_create(const hpt_config* cfg, void* arena, uint64_t arena_bytes, void* h
   // qr_rank_tol < 0: float64 form keeps CholeskyQR2 exact (any dependent
   // column sends the block to Householder), float32 form deflates columns
   // whose remaining pivot is below the float32 resolution of the Gram matrix
-  s->cfg_qr_tol = cfg->qr_rank_tol >= 0.0 ? cfg->qr_rank_tol : (s->fp32 ? 1e-12 : 0.0);
+  s->cfg_qr_tol = cfg->qr_rank_tol >= 0.0 ? cfg->qr_rank_tol : (s->fp32 ? 1e-14 : 0.0);
   // eps_cut < 0: 1e-11 (the paper's default) in the float64 form; in the
   // float32 form singular values near 1e-7 s_0 are rounding noise of the
   // float32 site tensors, so the cutoff is raised to 1e-7 s_0 there

@@ -296,6 +296,19 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdJob* jobs) {
   __syncthreads();
   const int n2 = n + (n & 1), npairs = n2 / 2;
   const double tol = 1e-15 * sqrt((double)m);
+  __shared__ double s_dead2;
+  {
+    double f = 0.0;
+    for (int idx = tid; idx < m * n; idx += blockDim.x) {
+      const double x = G[idx % m + (idx / m) * ldg];
+      f += x * x;
+    }
+    __shared__ double sh[16];
+    f = block_sum(f, sh);
+    if (tid == 0) s_dead2 = 1e-28 * f;
+    __syncthreads();
+  }
+  const double dead2 = s_dead2;
   int sweep = 0;
   if (n > 1) {
     for (sweep = 0; sweep < 60; ++sweep) {
@@ -316,7 +329,7 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdJob* jobs) {
           a = wave_sum(a);
           b = wave_sum(b);
           g = wave_sum(g);
-          if (g == 0.0 || !(fabs(g) > tol * sqrt(a * b))) continue;
+          if (g == 0.0 || !(fabs(g) > tol * sqrt(a * b)) || !(fmin(a, b) > dead2)) continue;
           double c, s;
           jacobi_rotation(a, b, g, c, s);
           for (int i = lane; i < m; i += 64) {
@@ -364,11 +377,21 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdJob* jobs) {
 // of one job: it loads the 2w columns into LDS, runs one inner Jacobi sweep
 // over all their pairs (one wave per pair), accumulates the 2w x 2w rotation
 // J, writes the columns back and applies J to the same columns of V.
-__global__ void bj_init_kernel(const SvdJob* jobs) {
+__global__ __launch_bounds__(256) void bj_init_kernel(const SvdJob* jobs) {
   const SvdJob job = jobs[blockIdx.x];
   for (int idx = threadIdx.x; idx < job.n * job.n; idx += blockDim.x) {
     const int i = idx % job.n, j = idx / job.n;
     job.V[i + (int64_t)j * job.ldv] = (i == j) ? 1.0 : 0.0;
+  }
+  if (job.fro2) {
+    __shared__ double sh[16];
+    double f = 0.0;
+    for (int64_t idx = threadIdx.x; idx < (int64_t)job.m * job.n; idx += blockDim.x) {
+      const double x = job.G[idx % job.m + (idx / job.m) * job.ldg];
+      f += x * x;
+    }
+    f = block_sum(f, sh);
+    if (threadIdx.x == 0) *job.fro2 = f;
   }
   if (threadIdx.x == 0) {
     job.state[0] = job.n < 2;
@@ -423,6 +446,7 @@ __global__ __launch_bounds__(1024) void bj_round_kernel(const SvdJob* jobs, int 
   for (int idx = tid; idx < W2 * W2; idx += blockDim.x) J[idx] = (idx % W2 == idx / W2) ? 1.0 : 0.0;
   __syncthreads();
   const double tol = 1e-15 * sqrt((double)m);
+  const double dead2 = job.fro2 ? 1e-28 * *job.fro2 : 0.0;
   const int nc2 = nc + (nc & 1);
   for (int r = 0; r < nc2 - 1; ++r) {
     for (int k = wave; k < nc2 / 2; k += nw) {
@@ -441,7 +465,7 @@ __global__ __launch_bounds__(1024) void bj_round_kernel(const SvdJob* jobs, int 
       x2 = wave_sum(x2);
       y2 = wave_sum(y2);
       xy = wave_sum(xy);
-      if (xy == 0.0 || !(fabs(xy) > tol * sqrt(x2 * y2))) continue;
+      if (xy == 0.0 || !(fabs(xy) > tol * sqrt(x2 * y2)) || !(fmin(x2, y2) > dead2)) continue;
       double c, sn;
       jacobi_rotation(x2, y2, xy, c, sn);
       for (int i = lane; i < m; i += 64) {
@@ -802,7 +826,19 @@ int launch_jacobi_svd(const SvdJob* jobs, int njobs, hipStream_t s) {
   return 0;
 }
 
-int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, hipStream_t s) {
+// done = 1 when every job has converged
+__global__ __launch_bounds__(256) void bj_all_done_kernel(const SvdJob* jobs, int njobs, int* done) {
+  __shared__ int s_all;
+  if (threadIdx.x == 0) s_all = 1;
+  __syncthreads();
+  for (int j = threadIdx.x; j < njobs; j += blockDim.x)
+    if (!jobs[j].state[0]) s_all = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) *done = s_all;
+}
+
+int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, hipStream_t s, int* done_dev,
+                            volatile int* done_host) {
   if (njobs <= 0) return 0;
   int mmax = 1, nmax = 1;
   for (int j = 0; j < njobs; ++j) {
@@ -833,6 +869,23 @@ int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, h
       hipLaunchKernelGGL(bj_round_kernel, dim3(std::max(1, nb2 / 2), njobs), dim3(1024), lds, s, jobs, r,
                          sweep, w);
       HPT_LAUNCH_CHECK("bj_round_kernel");
+    }
+    // from the fourth sweep on, stop launching once every job has converged
+    // (the check after sweep k sees the rotations of sweep k - 1)
+    if (done_dev && done_host && sweep >= 3 && sweep + 1 < max_sweeps) {
+      hipLaunchKernelGGL(bj_sweep_begin_kernel, dim3(njobs), dim3(64), 0, s, jobs, sweep + 1);
+      HPT_LAUNCH_CHECK("bj_sweep_begin_kernel");
+      hipLaunchKernelGGL(bj_all_done_kernel, dim3(1), dim3(256), 0, s, jobs, njobs, done_dev);
+      HPT_LAUNCH_CHECK("bj_all_done_kernel");
+      HPT_HIP(hipMemcpyAsync((void*)done_host, done_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+      HPT_HIP(hipStreamSynchronize(s));
+      if (*done_host) break;
+      ++sweep;   // that sweep has begun: run its rounds next
+      for (int r = 0; r < nb2 - 1; ++r) {
+        hipLaunchKernelGGL(bj_round_kernel, dim3(std::max(1, nb2 / 2), njobs), dim3(1024), lds, s, jobs, r,
+                           sweep, w);
+        HPT_LAUNCH_CHECK("bj_round_kernel");
+      }
     }
   }
   hipLaunchKernelGGL(bj_finish_kernel, dim3(njobs), dim3(1024), 0, s, jobs);

@@ -40,7 +40,12 @@ struct SvdJob {
   double* s; int* perm;
   int* sweeps;
   int* state;          // 3 ints of scratch for the block variant (done, 2 rotation counters)
+  double* fro2;        // block variant: 1 double of scratch (squared Frobenius norm); may be null
 };
+// Columns whose norm falls below 1e-14 of the Frobenius norm of G hold only
+// rounding noise: pairs involving them are not rotated (otherwise the noise
+// columns keep exchanging rounding errors with the large ones and the
+// sweeps never settle).  Their singular values are reported as computed.
 
 // Upper Cholesky G = R^T R of an n x n SPD block (G read, R written, may alias).
 // *info = 0 on success, j+1 if pivot j fails the relative test.
@@ -103,7 +108,11 @@ int launch_jacobi_svd(const SvdJob* jobs, int njobs, hipStream_t s);
 // Block one-sided Jacobi: every launch of a round pairs column blocks of all
 // jobs, one workgroup per block pair with the block columns in LDS.  Needs
 // SvdJob::state; host holds the host copies of the jobs (sizes).
-int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, hipStream_t s);
+// With done_dev (device int) and done_host (pinned host int), the host checks
+// convergence once per sweep from the fourth sweep on (one stream sync each)
+// and stops launching when every job has converged.
+int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, hipStream_t s, int* done_dev,
+                            volatile int* done_host);
 int launch_cholesky(const CholJob* jobs, int njobs, double rel_tol, hipStream_t s);
 int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s);
 int launch_piv_cholesky(const PivCholJob* jobs, int njobs, hipStream_t s);

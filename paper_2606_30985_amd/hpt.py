@@ -31,6 +31,8 @@ FLAGS = {
     "BETHE_ZERO": 1 << 6,
     "QR_FALLBACK": 1 << 7,
     "QR_RANK_DEFICIENT": 1 << 8,
+    "TRAP_REMEDIATED": 1 << 9,
+    "TRAP_UNRESOLVED": 1 << 10,
 }
 
 
@@ -47,7 +49,8 @@ class HptConfig(ctypes.Structure):
         ("meas_alpha", ctypes.c_double), ("meas_tol", ctypes.c_double),
         ("meas_max_sweeps", ctypes.c_int32), ("gauge_bp", ctypes.c_int32),
         ("trap_sweeps", ctypes.c_int32), ("qr_rank_tol", ctypes.c_double),
-        ("reserved", ctypes.c_int32 * 6),
+        ("trap_retry", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("trap_alpha", ctypes.c_double),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 

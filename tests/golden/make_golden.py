@@ -20,6 +20,9 @@ CASES = {
     "oracle_4x4_chi20": (dict(Lx=4, Ly=4, J=1.0, h=1.0, dt=0.05, chi_max=20, bp_alpha=0.5, bp_tol=1e-10), 40),
     "oracle_4x4_chi40": (dict(Lx=4, Ly=4, J=1.0, h=1.0, dt=0.05, chi_max=40, bp_alpha=0.5, bp_tol=1e-10), 40),
     "oracle_3x3_chi8": (dict(Lx=3, Ly=3, J=1.0, h=1.0, dt=0.05, chi_max=8, bp_alpha=0.5, bp_tol=1e-10), 20),
+    # the 4x4 chi_max 20 run with the trap remediation (the layer-40 trap is retried)
+    "oracle_4x4_chi20_trap_retry": (dict(Lx=4, Ly=4, J=1.0, h=1.0, dt=0.05, chi_max=20, bp_alpha=0.5, bp_tol=1e-10,
+                                         trap_retry=True), 40),
 }
 
 BOND_CASES = ("oracle_bond_4x4_chi100",)

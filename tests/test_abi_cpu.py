@@ -30,11 +30,12 @@ def test_config_defaults(hpt):
     assert (c.Lx, c.Ly, c.chi_max) == (3, 3, 8)
     assert c.eps_cut == -1.0 and c.bp_alpha == 0.5 and c.bp_tol == 1e-10
     assert c.cx == -1 and c.cy == -1 and c.trap_sweeps == 30
+    assert c.trap_retry == 0 and c.trap_alpha == -1.0 and c.qr_rank_tol == -1.0
 
 
 @pytest.mark.parametrize("kw", [dict(Lx=1, Ly=1), dict(Lx=0, Ly=3), dict(dt=0.0), dict(chi_max=0),
                                 dict(cx=3, cy=0), dict(precision=7), dict(bp_alpha=0.0),
-                                dict(bp_tol=-1.0), dict(chi_max=300)])
+                                dict(bp_tol=-1.0), dict(chi_max=300), dict(trap_retry=2), dict(trap_alpha=1.5)])
 def test_invalid_configs_rejected(hpt, kw):
     c = hpt.make_config(**kw)
     n = ctypes.c_uint64()

@@ -67,17 +67,39 @@ def test_config0_fp32_form():
     # the arithmetic alone
     got = _traj(hpt, cfg, g["nsteps"], precision="fp32", eps_cut=1e-9)
     worst = max(abs(got[k]["C"] - rec["C"]) for k, rec in enumerate(g["records"]))
-    print("fp32 form worst |dC| on 3x3 chi 8:", worst)
+    print("fp32 form worst |dC| on 3x3 chi 8:", worst, "per layer:",
+          " ".join(f"{abs(got[k]['C'] - rec['C']):.1e}" for k, rec in enumerate(g["records"])))
     assert worst <= 2e-6
 
 
 def test_config1_chi20_fp32_form():
-    # the float32 form on 4x4 chi 20: |dC| against the float64 oracle, first 30 layers
+    # the float32 form on 4x4 chi 20: |dC| against the float64 oracle, first
+    # 30 layers.  Up to t = 0.9 (layer 18) the difference stays at the level
+    # set by the float32 gauge BP (converged to 1e-6, its float32 floor, so
+    # the gauge and through it the Bethe estimate differ by ~1e-6); later
+    # every layer truncates (gate error ~1e-3), and rounding-level changes of
+    # the spectrum at the cut move C(t) by up to about 1e-5
     hpt = load_hpt()
     g = _golden("oracle_4x4_chi20")
     cfg = dict(g["config"])
     cfg["bp_tol"] = 1e-6
     got = _traj(hpt, cfg, 30, precision="fp32")
-    worst = max(abs(got[k]["C"] - g["records"][k]["C"]) for k in range(31))
-    print("fp32 form worst |dC| on 4x4 chi 20 (30 layers):", worst)
-    assert worst <= 1e-5
+    d = [abs(got[k]["C"] - g["records"][k]["C"]) for k in range(31)]
+    print("fp32 form |dC| on 4x4 chi 20 per layer:", " ".join(f"{x:.1e}" for x in d))
+    assert max(d[:19]) <= 4e-6
+    assert max(d) <= 5e-5
+
+
+def test_config1_chi20_trap_retry():
+    # trap remediation on the 4x4 chi 20 run: at layer 40 both BPs converge
+    # yet C(t) falls from 0.062 to 0.0066 with a gate error barely larger;
+    # the measurement BP rerun at damping 0.8 returns to the smooth sequence
+    # (0.0604).  Same rule on both sides, FP64 parity on every layer.
+    hpt = load_hpt()
+    g = _golden("oracle_4x4_chi20_trap_retry")
+    got = _traj(hpt, g["config"], g["nsteps"])
+    for k, rec in enumerate(g["records"]):
+        assert abs(got[k]["C"] - rec["C"]) <= 1e-10, (k, got[k]["C"], rec["C"])
+        assert bool(got[k]["flags"] & hpt.FLAGS["TRAP_REMEDIATED"]) == bool(rec["flags"] & hpt.FLAGS["TRAP_REMEDIATED"])
+    assert got[-1]["flags"] & hpt.FLAGS["TRAP_REMEDIATED"]
+    assert 0.05 < got[-1]["C"] < 0.07

@@ -196,3 +196,36 @@ def test_paper_printed_universal_value_5x5():
     net, recs = _run_net(Config(Lx=5, Ly=5, chi_max=8, dt=0.1, J=-1.0, h=-1.0,
                                  bp_tol=1e-6, bp_max_sweeps=100), 9)
     assert abs(recs[-1]["C"] - target) <= 5e-4 + 2e-4
+
+
+def test_trap_rule_on_records():
+    # the remediation rule (paper, trap remediation steps 1-3) on plain records
+    from oracle.network import Config, FLAG_TRAP_CANDIDATE
+    from oracle.run import trap_verified, retry_alpha
+    prev = dict(C=0.0622, gate_err=0.0054, flags=0)
+    trapped = dict(C=0.0066, gate_err=0.0067, flags=FLAG_TRAP_CANDIDATE)
+    assert trap_verified(trapped, prev)
+    assert not trap_verified(dict(trapped, flags=0), prev)               # not a candidate
+    assert not trap_verified(dict(trapped, C=0.04), prev)                # drop of less than half
+    assert not trap_verified(dict(trapped, gate_err=0.02), prev)         # gate error grew in proportion
+    assert not trap_verified(trapped, None)
+    assert retry_alpha(Config(bp_alpha=0.5)) == 0.8
+    assert retry_alpha(Config(bp_alpha=1.0)) == 0.5
+    assert retry_alpha(Config(bp_alpha=0.5, trap_alpha=0.7)) == 0.7
+
+
+def test_trap_retry_golden_continues_the_smooth_sequence():
+    # the oracle run with the remediation (written by tests/golden/make_golden.py):
+    # layers 1..39 equal the run without it, and the retried layer 40 lies on
+    # the quadratic continuation of layers 37..39 (the trapped value does not)
+    import json, os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    a = json.load(open(os.path.join(here, "oracle_4x4_chi20.json")))["records"]
+    b = json.load(open(os.path.join(here, "oracle_4x4_chi20_trap_retry.json")))["records"]
+    for k in range(40):
+        assert abs(a[k]["C"] - b[k]["C"]) <= 1e-13
+    c37, c38, c39 = (b[k]["C"] for k in (37, 38, 39))
+    extrap = 3 * c39 - 3 * c38 + c37
+    assert abs(b[40]["C"] - extrap) < 2e-3
+    assert abs(a[40]["C"] - extrap) > 0.05
+    assert b[40]["flags"] & (1 << 9)
