@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--trace", default="", help="append per-step records (JSON lines) to this file")
     ap.add_argument("--profile-all", action="store_true",
                     help="kernel event profile over every layer (warm-up included), for counter comparisons")
+    ap.add_argument("--workload", default="large", choices=["large", "batched"],
+                    help="large: the 10x10 chi=100 run (default); batched: the independent-runs set")
+    ap.add_argument("--batch-runs", type=int, default=64)
+    ap.add_argument("--batch-chi", type=int, default=40)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="first copy this many bytes with the library's plain copy kernel (counter calibration)")
     return ap.parse_args()
@@ -115,8 +119,64 @@ def traffic_ratio(kernel_key):
     return ratio
 
 
+def batched(args):
+    """The batched form: independent runs (grid 3x3..6x6, h ~ U[0.5, 3], dt in
+    {0.025, 0.05, 0.1, 0.2}, total time 2, chi_max 40, FP32 form), measured
+    after every layer.  Timed twice on the same handles: one run after
+    another, then all at once through hpt_run_batch; the trajectories must
+    agree exactly."""
+    import torch
+    from paper_2606_30985_amd import hpt, inputs
+    runs = inputs.batched_runs()[: args.batch_runs]
+    sims = [hpt.Simulator(Lx=r["Lx"], Ly=r["Ly"], J=r["J"], h=r["h"], dt=r["dt"], chi_max=args.batch_chi,
+                          precision="fp32", bp_tol=args.bp_tol, bp_max_sweeps=args.bp_max_sweeps, bp_alpha=0.5,
+                          bp_init=args.bp_init, meas_tol=args.meas_tol, meas_max_sweeps=args.meas_max_sweeps,
+                          stream=torch.cuda.Stream())
+            for r in runs]
+    nsteps = [r["nsteps"] for r in runs]
+    total = sum(nsteps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = []
+    for i, (s, n) in enumerate(zip(sims, nsteps)):
+        traj = []
+        for _ in range(n):
+            s.step(1)
+            traj.append(s.measure()["C"])
+        seq.append(traj)
+        print(f"# sequential run {i}: {runs[i]['Lx']}x{runs[i]['Ly']} dt={runs[i]['dt']} {n} layers "
+              f"C(2)={traj[-1]:.8f} {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for s in sims:
+        s.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = hpt.run_batch(sims, nsteps)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    print(f"# batched: {t_bat:.2f} s (sequential {t_seq:.2f} s)", file=sys.stderr, flush=True)
+    dmax = max(abs(a - b["C"]) for traj, rr in zip(seq, res) for a, b in zip(traj, rr))
+    for s in sims:
+        s.close()
+    out = {"metric": "Trotter layers/sec, batched form (independent runs, MPF step-size set)",
+           "value": total / t_bat, "unit": "layers/s", "n_gpus": 1, "steps": total, "warmup": 0,
+           "ms_per_step": 1e3 * t_bat / total, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded run parameters, deterministic initial operators)",
+           "config": {"workload": f"{len(runs)} independent runs, grids 3x3..6x6, h ~ U[0.5,3], dt in "
+                                  f"{{0.025,0.05,0.1,0.2}}, t = 2, chi_max={args.batch_chi}, FP32 form",
+                      "layers": total, "sequential_layers_per_s": total / t_seq, "speedup_vs_sequential": t_seq / t_bat,
+                      "max_abs_dC_batched_vs_sequential": dmax}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "batched":
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; run with --gpus 1"}))
+            sys.exit(2)
+        return batched(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only "
                                    "(DESIGN.md), run with --gpus 1"}))

@@ -193,6 +193,19 @@ int hpt_set_messages(hpt_sim* sim, int32_t bond, int32_t dir, const double* host
 /* Measurement message (vector of length chi) of the last hpt_measure. */
 int hpt_get_meas_messages(hpt_sim* sim, int32_t bond, int32_t dir, double* host, int32_t cap);
 
+/* Batched form (independent runs, e.g. the step sizes of a multi-product-formula
+ * set): advances every handle sims[i] by nsteps[i] layers, concurrently: a pool
+ * of up to 16 host threads takes the runs in order, each run on its handle's
+ * own stream, so the kernels of different runs overlap on the device.  When
+ * out != NULL and out[i] != NULL, out[i][k] receives hpt_measure after layer k
+ * of run i (caller-owned, nsteps[i] records).  Handles must be distinct; runs
+ * are independent, so each trajectory equals the one hpt_step/hpt_measure
+ * give for that handle alone.  Returns HPT_EINVAL for null or repeated
+ * handles or a negative count, HPT_ESTATE while the contraction profile is
+ * enabled (its counters are process-wide), else the first error of any run
+ * (the other runs stop at their next layer).  Blocks until all runs are done. */
+int hpt_run_batch(hpt_sim* const* sims, int32_t n, const int32_t* nsteps, hpt_measurement* const* out);
+
 int hpt_destroy(hpt_sim* sim);
 
 const char* hpt_strerror(int code);

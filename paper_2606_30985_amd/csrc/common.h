@@ -57,6 +57,7 @@ int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s);
 // 1 its float64-accumulated Gram, 2 mode_product_kernel, 3 leg_gram_kernel, -1 all
 int gemm_profile(int enable);
 int gemm_profile_read(int kind, double* out4);
+int gemm_profile_active();
 
 // Mode product of the float32 form, dst = src x_axis S with the n x n factor
 // S resident in LDS: dst[a, j, b] = sum_k S[j, k] src[a, k, b] for a < inner,

@@ -14,6 +14,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
+#include <atomic>
 #include <vector>
 
 #include "engine.h"
@@ -922,8 +924,8 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
       else
         j = SmallGemmJob{q1, q0, K, nullptr, nullptr, nullptr, bc.Tm[1], ldR, 0, bc.Tm[0], ldR, 1, bc.G, ldR, 1.0, 0.0, nullptr};
       gj.push_back(j);
-      sj.push_back(SvdJob{bc.G, ldR, std::max(q0, q1), std::min(q0, q1), bc.V, ldR, bc.s, bc.perm, nullptr,
-                          s->slots[q].svd_state, (double*)(s->slots[q].svd_state + 8)});
+      sj.push_back(SvdJob{bc.G, ldR, std::max(q0, q1), std::min(q0, q1), bc.V, ldR, bc.s, bc.perm,
+                          s->slots[q].svd_state + 4, s->slots[q].svd_state, (double*)(s->slots[q].svd_state + 8)});
     }
     SmallGemmJob* gd;
     RC(stage(s, gj.data(), nb, &gd));
@@ -997,7 +999,21 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
   for (int q = 0; q < nb; ++q)
     HPT_HIP(hipMemcpyAsync(s->hscratch + ncut_off + q * 64, s->slots[q].ncut, 6 * sizeof(int),
                            hipMemcpyDeviceToHost, s->stream));
+  static const bool dbg_svd = getenv("HPT_DEBUG_SVD") != nullptr;
+  if (dbg_svd)
+    for (int q = 0; q < nb; ++q)
+      HPT_HIP(hipMemcpyAsync(s->hscratch + ncut_off + q * 64 + 32, s->slots[q].svd_state + 4, sizeof(int),
+                             hipMemcpyDeviceToHost, s->stream));
   RC(sync_stream(s));
+  if (dbg_svd) {
+    int mx = 0, sum = 0;
+    for (int q = 0; q < nb; ++q) {
+      const int sw = *(const int*)(s->hscratch + ncut_off + q * 64 + 32);
+      mx = std::max(mx, sw);
+      sum += sw;
+    }
+    fprintf(stderr, "[svd] step %d colour bonds %d: Jacobi sweeps max %d mean %.1f\n", s->step, nb, mx, (double)sum / nb);
+  }
   std::memcpy(cores.data(), s->hscratch, core_bytes);
   for (int q = 0; q < nb; ++q) {
     const int b = cbonds[q];
@@ -1624,6 +1640,44 @@ int hpt_step(hpt_sim* s, int32_t nsteps) {
     if (r) return r;
   }
   return HPT_OK;
+}
+
+int hpt_run_batch(hpt_sim* const* sims, int32_t n, const int32_t* nsteps, hpt_measurement* const* out) {
+  if (!sims || !nsteps || n < 0) return HPT_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!sims[i] || nsteps[i] < 0) return HPT_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (sims[j] == sims[i]) return HPT_EINVAL;
+  }
+  if (gemm_profile_active()) return HPT_ESTATE;
+  // a pool of host threads, each driving whole runs on their own streams
+  std::atomic<int> next(0), err(0);
+  auto worker = [&]() {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= n || err.load() != 0) return;
+      hpt_sim* s = sims[i];
+      for (int k = 0; k < nsteps[i]; ++k) {
+        int r = s->fp32 ? layer_t<float>(s) : layer_t<double>(s);
+        if (!r && out && out[i]) r = s->fp32 ? measure_t<float>(s, out[i] + k) : measure_t<double>(s, out[i] + k);
+        if (r) {
+          int z = 0;
+          err.compare_exchange_strong(z, r);
+          return;
+        }
+      }
+      if (hipStreamSynchronize(s->stream) != hipSuccess) {
+        int z = 0;
+        err.compare_exchange_strong(z, (int)HPT_EHIP);
+        return;
+      }
+    }
+  };
+  const int nt = std::max(1, std::min<int>(n, 16));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
+  for (auto& t : pool) t.join();
+  return err.load();
 }
 
 int hpt_apply_field(hpt_sim* s) {

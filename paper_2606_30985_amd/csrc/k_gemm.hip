@@ -628,6 +628,8 @@ int gemm_profile(int enable) {
   return 0;
 }
 
+int gemm_profile_active() { return g_prof.on; }
+
 int gemm_profile_read(int kind, double* out4) {
   if (kind < -1 || kind >= PROF_KINDS) return -1;
   if (g_prof.on) {

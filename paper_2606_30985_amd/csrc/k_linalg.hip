@@ -287,7 +287,7 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdJob* jobs) {
   double* V = job.V;
   const int ldg = job.ldg, ldv = job.ldv;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-  __shared__ int s_rot;
+  __shared__ int s_rot, s_off;
   __shared__ double s_sig[1024];
   for (int idx = tid; idx < n * n; idx += blockDim.x) {
     const int i = idx % n, j = idx / n;
@@ -312,7 +312,10 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdJob* jobs) {
   int sweep = 0;
   if (n > 1) {
     for (sweep = 0; sweep < 60; ++sweep) {
-      if (tid == 0) s_rot = 0;
+      if (tid == 0) {
+        s_rot = 0;
+        s_off = 0;
+      }
       __syncthreads();
       for (int r = 0; r < n2 - 1; ++r) {
         for (int k = wave; k < npairs; k += nw) {
@@ -329,7 +332,10 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdJob* jobs) {
           a = wave_sum(a);
           b = wave_sum(b);
           g = wave_sum(g);
-          if (g == 0.0 || !(fabs(g) > tol * sqrt(a * b)) || !(fmin(a, b) > dead2)) continue;
+          if (!(fmin(a, b) > dead2)) continue;
+          const double rel = fabs(g) / sqrt(a * b);
+          if (lane == 0 && rel == rel) atomicMax(&s_off, __float_as_int((float)fmin(rel, 1.0)));
+          if (g == 0.0 || !(fabs(g) > tol * sqrt(a * b))) continue;
           double c, s;
           jacobi_rotation(a, b, g, c, s);
           for (int i = lane; i < m; i += 64) {
@@ -346,10 +352,12 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdJob* jobs) {
         }
         __syncthreads();
       }
-      if (!s_rot) break;
+      // no rotation, or every relative off-diagonal met in this sweep < 1e-12
+      if (!s_rot || __int_as_float(s_off) < 1e-12f) break;
       __syncthreads();
     }
   }
+  if (tid == 0 && job.sweeps) *job.sweeps = sweep + 1;
   for (int p = wave; p < n; p += nw) {
     double a = 0.0;
     for (int i = lane; i < m; i += 64) a += G[i + p * ldg] * G[i + p * ldg];
@@ -397,6 +405,8 @@ __global__ __launch_bounds__(256) void bj_init_kernel(const SvdJob* jobs) {
     job.state[0] = job.n < 2;
     job.state[1] = 0;
     job.state[2] = 0;
+    job.state[5] = 0;
+    job.state[6] = 0;
     if (job.sweeps) *job.sweeps = 0;
   }
 }
@@ -404,11 +414,16 @@ __global__ __launch_bounds__(256) void bj_init_kernel(const SvdJob* jobs) {
 __global__ void bj_sweep_begin_kernel(const SvdJob* jobs, int sweep) {
   const SvdJob job = jobs[blockIdx.x];
   if (threadIdx.x != 0 || job.state[0]) return;
-  if (sweep > 0 && job.state[1 + ((sweep - 1) & 1)] == 0) {
+  // done after a sweep without rotations, or one whose largest relative
+  // off-diagonal |<g_p, g_q>| / (|g_p| |g_q|) stayed below 1e-12 (the
+  // remaining rotations only shuffle rounding between near-degenerate columns)
+  if (sweep > 0 && (job.state[1 + ((sweep - 1) & 1)] == 0 ||
+                    __int_as_float(job.state[5 + ((sweep - 1) & 1)]) < 1e-12f)) {
     job.state[0] = 1;
     return;
   }
   job.state[1 + (sweep & 1)] = 0;
+  job.state[5 + (sweep & 1)] = 0;
   if (job.sweeps) *job.sweeps = sweep + 1;
 }
 
@@ -426,7 +441,7 @@ __global__ __launch_bounds__(1024) void bj_round_kernel(const SvdJob* jobs, int 
   double* J = lds;                 // W2 x W2, J[u + W2 t]
   double* Gs = lds + W2 * W2;      // column t at Gs + t * m
   __shared__ int cols[64];
-  __shared__ int s_nc, s_rot;
+  __shared__ int s_nc, s_rot, s_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   if (tid == 0) {
     int nc = 0;
@@ -436,6 +451,7 @@ __global__ __launch_bounds__(1024) void bj_round_kernel(const SvdJob* jobs, int 
       if (Q * w + t < n) cols[nc++] = Q * w + t;
     s_nc = nc;
     s_rot = 0;
+    s_off = 0;
   }
   __syncthreads();
   const int nc = s_nc;
@@ -465,7 +481,10 @@ __global__ __launch_bounds__(1024) void bj_round_kernel(const SvdJob* jobs, int 
       x2 = wave_sum(x2);
       y2 = wave_sum(y2);
       xy = wave_sum(xy);
-      if (xy == 0.0 || !(fabs(xy) > tol * sqrt(x2 * y2)) || !(fmin(x2, y2) > dead2)) continue;
+      if (!(fmin(x2, y2) > dead2)) continue;
+      const double rel = fabs(xy) / sqrt(x2 * y2);
+      if (lane == 0 && rel == rel) atomicMax(&s_off, __float_as_int((float)fmin(rel, 1.0)));
+      if (xy == 0.0 || !(fabs(xy) > tol * sqrt(x2 * y2))) continue;
       double c, sn;
       jacobi_rotation(x2, y2, xy, c, sn);
       for (int i = lane; i < m; i += 64) {
@@ -482,6 +501,7 @@ __global__ __launch_bounds__(1024) void bj_round_kernel(const SvdJob* jobs, int 
     }
     __syncthreads();
   }
+  if (tid == 0) atomicMax(&job.state[5 + (sweep & 1)], s_off);
   if (!s_rot) return;
   for (int idx = tid; idx < nc * m; idx += blockDim.x) {
     const int t = idx / m, i = idx % m;

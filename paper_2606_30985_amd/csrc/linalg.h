@@ -39,7 +39,8 @@ struct SvdJob {
   double* V; int ldv;
   double* s; int* perm;
   int* sweeps;
-  int* state;          // 3 ints of scratch for the block variant (done, 2 rotation counters)
+  int* state;          // 7 ints of scratch for the block variant (done, 2 rotation counters, -, -,
+                       // 2 largest relative off-diagonals as float bits)
   double* fro2;        // block variant: 1 double of scratch (squared Frobenius norm); may be null
 };
 // Columns whose norm falls below 1e-14 of the Frobenius norm of G hold only

@@ -100,6 +100,7 @@ def _load():
         "hpt_profile_gemm": [i32],
         "hpt_profile_gemm_read": [ctypes.POINTER(dbl)],
         "hpt_profile_read": [i32, ctypes.POINTER(dbl)],
+        "hpt_run_batch": [ctypes.POINTER(ctypes.c_void_p), i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_void_p)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -119,7 +120,7 @@ EXPORTED = ["hpt_config_default", "hpt_required_bytes", "hpt_state_bytes", "hpt_
             "hpt_measure", "hpt_get_chi", "hpt_get_bond_spectrum", "hpt_get_site_tensor",
             "hpt_set_site_tensor", "hpt_get_messages", "hpt_set_messages",
             "hpt_get_meas_messages", "hpt_destroy", "hpt_strerror", "hpt_last_hip_error",
-            "hpt_permute", "hpt_profile_gemm", "hpt_profile_gemm_read", "hpt_profile_read"]
+            "hpt_permute", "hpt_profile_gemm", "hpt_profile_gemm_read", "hpt_profile_read", "hpt_run_batch"]
 
 
 def profile_gemm(enable=True):
@@ -135,6 +136,25 @@ def profile_gemm_read(kind=None):
     k = -1 if kind is None else PROF_KINDS[kind]
     check(lib.hpt_profile_read(k, out), "hpt_profile_read")
     return dict(launches=int(out[0]), ms=out[1], flops=out[2], bytes=out[3])
+
+
+def run_batch(sims, nsteps, measure=True):
+    """Advance independent handles concurrently (hpt_run_batch): sims[i] by
+    nsteps[i] layers; returns, per run, the measurement after every layer (or
+    None when measure is False).  Give each handle its own stream."""
+    n = len(sims)
+    if len(nsteps) != n:
+        raise ValueError("one step count per handle")
+    arr = (ctypes.c_void_p * n)(*[s.h.value for s in sims])
+    ns = (ctypes.c_int32 * n)(*[int(k) for k in nsteps])
+    outs, bufs = None, []
+    if measure:
+        bufs = [(HptMeasurement * max(int(k), 1))() for k in nsteps]
+        outs = (ctypes.c_void_p * n)(*[ctypes.cast(b, ctypes.c_void_p).value for b in bufs])
+    check(lib.hpt_run_batch(arr, n, ns, outs), "hpt_run_batch")
+    if not measure:
+        return None
+    return [[b[k].as_dict() for k in range(int(nsteps[i]))] for i, b in enumerate(bufs)]
 
 
 class HptError(RuntimeError):
@@ -182,7 +202,7 @@ def state_bytes(cfg):
 class Simulator:
     """One handle of libhpt on a CUDA/HIP device via PyTorch memory and stream."""
 
-    def __init__(self, cfg=None, device="cuda:0", torch_arena=True, **kw):
+    def __init__(self, cfg=None, device="cuda:0", torch_arena=True, stream=None, **kw):
         import torch
         self.torch = torch
         self.cfg = cfg if cfg is not None else make_config(**kw)
@@ -195,7 +215,8 @@ class Simulator:
             self.arena = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
             base = self.arena.data_ptr()
             ptr = (base + 255) // 256 * 256
-        self.stream = torch.cuda.current_stream(self.device)
+        # the handle's stream: the caller's (e.g. one per run of a batch) or torch's current one
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         check(lib.hpt_create(ctypes.byref(self.cfg), ptr, self.nbytes if ptr else 0,
                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "hpt_create")

@@ -64,3 +64,23 @@ def test_10x10_chi100_fp32_form_against_fp64():
     early = [r for r in cmp if r["t"] <= 1.0 + 1e-12]
     assert max(r["dC"] for r in early) <= 5e-6
     assert max(r["dC"] for r in cmp) <= 5e-5
+
+
+def test_10x10_chi30_fp64_against_oracle():
+    # the benchmark lattice at a bond dimension the CPU oracle can follow:
+    # 12 layers of the FP64 form against the oracle's trajectory
+    # (tests/golden/oracle_10x10_chi30.json), within 1e-10
+    import json
+    hpt = load_hpt()
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_10x10_chi30.json")
+    g = json.load(open(path))
+    sim = hpt.Simulator(precision="fp64", **g["config"])
+    got = [sim.measure()]
+    for _ in range(g["nsteps"]):
+        sim.step(1)
+        got.append(sim.measure())
+        print(f"# fp64 10x10 chi30 step {got[-1]['step']} C={got[-1]['C']:.12f}", file=sys.stderr, flush=True)
+    sim.close()
+    for k, rec in enumerate(g["records"]):
+        assert abs(got[k]["C"] - rec["C"]) <= 1e-10, (k, got[k]["C"], rec["C"])
+        assert got[k]["chi_live_max"] == rec["chi_live_max"]
