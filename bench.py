@@ -58,7 +58,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(chi, L, dt, sample_chi=30):
+def cpu_baseline(chi, L, dt, sample_chi=60):
     """CPU oracle on one interior-interior bond update (synthetic saturated
     inputs) at sample_chi, extrapolated to the workload's chi by the chi^5
     cost of the update and scaled to layers/s by the layer's bond count."""
@@ -102,12 +102,13 @@ def traffic_ratio(kernel_key):
     PMC summary; None when the kernel source has changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "mode_product_kernel_10x10_chi100_pmc.md")
-    if kernel_key != "mode" or not os.path.exists(path):
+    if not os.path.exists(path):
         return None
+    names = {"mode": "mode_product_kernel", "gram64": "gram64", "leggram": "leggram", "gemm": "gemm"}
     ratio = sha = src = None
     for line in open(path):
         f = line.split()
-        if len(f) == 3 and f[0] == "traffic_ratio" and f[1] == "mode_product_kernel":
+        if len(f) == 3 and f[0] == "traffic_ratio" and f[1] == names.get(kernel_key):
             ratio = float(f[2])
         if len(f) == 3 and f[0] == "kernel_source_sha256":
             src, sha = f[1], f[2]
@@ -124,7 +125,7 @@ def batched(args):
     {0.025, 0.05, 0.1, 0.2}, total time 2, chi_max 40, FP32 form), measured
     after every layer.  Timed twice on the same handles: one run after
     another, then all at once through hpt_run_batch; the trajectories must
-    agree exactly."""
+    agree exactly.  Batched first (fresh handles), then one after another."""
     import torch
     from paper_2606_30985_amd import hpt, inputs
     runs = inputs.batched_runs()[: args.batch_runs]
@@ -135,6 +136,15 @@ def batched(args):
             for r in runs]
     nsteps = [r["nsteps"] for r in runs]
     total = sum(nsteps)
+    os.environ["HPT_BATCH_PROGRESS"] = "1"   # one line per finished run
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = hpt.run_batch(sims, nsteps)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    print(f"# batched: {t_bat:.2f} s", file=sys.stderr, flush=True)
+    for s in sims:
+        s.reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     seq = []
@@ -148,14 +158,7 @@ def batched(args):
               f"C(2)={traj[-1]:.8f} {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
-    for s in sims:
-        s.reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = hpt.run_batch(sims, nsteps)
-    torch.cuda.synchronize()
-    t_bat = time.perf_counter() - t0
-    print(f"# batched: {t_bat:.2f} s (sequential {t_seq:.2f} s)", file=sys.stderr, flush=True)
+    print(f"# sequential: {t_seq:.2f} s (batched {t_bat:.2f} s)", file=sys.stderr, flush=True)
     dmax = max(abs(a - b["C"]) for traj, rr in zip(seq, res) for a, b in zip(traj, rr))
     for s in sims:
         s.close()

@@ -67,6 +67,7 @@ struct BondSlot {
   double* z;
   double* lam;
   int* svd_state;
+  double* pq[4];    // preconditioned core SVD scratch (4 chi_max x 4 chi_max each)
   // float32 form: float64 scratch of the batched CholeskyQR2 steps, per side
   double* qa[2][8];
   int* qsel[2];

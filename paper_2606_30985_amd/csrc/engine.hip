@@ -160,6 +160,10 @@ uint64_t slot_layout(int C, bool fp32, char* base, BondSlot* sl) {
   void* z = take(n4 * 4 * 8);
   void* lam = take((uint64_t)C * 8);
   void* sst = take(64);
+  for (int a = 0; a < 4; ++a) {
+    void* q = take(n4 * n4 * 8);
+    if (sl) sl->pq[a] = (double*)q;
+  }
   for (int i = 0; i < 2; ++i) {
     for (int a = 0; a < 8; ++a) {
       void* q = fp32 ? take(n4 * n4 * 8) : nullptr;
@@ -825,6 +829,7 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
       bc.bqr[i] = (s->fp32 && P.k >= bc.chi_cut) ? 0 : 1;
       for (int a = 0; a < 8; ++a) bc.qs[i][a] = sl.qa[i][a];
     }
+    for (int a = 0; a < 4; ++a) bc.pq[a] = sl.pq[a];
     bc.chi_max = C;
     bc.eps_cut = s->cfg.eps_cut;
     bc.ldR = ldR;
@@ -930,16 +935,40 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
     SmallGemmJob* gd;
     RC(stage(s, gj.data(), nb, &gd));
     KR(launch_small_gemm(gd, gj.data(), nb, s->stream));
-    SvdJob* sd;
-    RC(stage(s, sj.data(), nb, &sd));
-    // block Jacobi (many workgroups per SVD) when any core is wider than 64
+    // block Jacobi (many workgroups per SVD) when any core is wider than 64,
+    // preconditioned: QR of the core, Jacobi on R^T (a graded core needs ~3x
+    // fewer sweeps there), then back to the core's singular vectors
     int nmax = 0;
     for (auto& j : sj) nmax = std::max(nmax, j.n);
-    if (nmax > 64)
+    if (nmax > 64) {
+      std::vector<QrJob<double>> qj;
+      std::vector<SmallGemmJob> back;
+      for (int q = 0; q < nb; ++q) {
+        const BondCore& bc = cores[q];
+        const int m = sj[q].m, n = sj[q].n;
+        qj.push_back(QrJob<double>{bc.G, ldR, m, n, bc.pq[0], ldR, s->slots[q].tau, 1, nullptr, 0});
+        sj[q].G = bc.pq[1];
+        sj[q].m = n;
+        sj[q].V = bc.pq[3];
+        back.push_back(SmallGemmJob{m, n, n, nullptr, nullptr, nullptr, bc.pq[2], ldR, 0, bc.pq[0], ldR, 0, bc.G, ldR,
+                                    1.0, 0.0, nullptr, 0});
+      }
+      QrJob<double>* qd;
+      RC(stage(s, qj.data(), nb, &qd));
+      KR(launch_householder<double>(qd, nb, s->stream));
+      KR(launch_rcore_precond_prep(cd, nb, s->stream));
+      SvdJob* sd;
+      RC(stage(s, sj.data(), nb, &sd));
       KR(launch_block_jacobi_svd(sd, sj.data(), nb, s->stream, (int*)(s->res + 12),
                                  (volatile int*)(s->hscratch + s->hscratch_bytes - 64)));
-    else
+      KR(launch_rcore_precond_finish(cd, nb, s->stream));
+      RC(stage(s, back.data(), nb, &gd));
+      KR(launch_small_gemm(gd, back.data(), nb, s->stream));
+    } else {
+      SvdJob* sd;
+      RC(stage(s, sj.data(), nb, &sd));
       KR(launch_jacobi_svd(sd, nb, s->stream));
+    }
   }
   KR(launch_rcore_select(cd, nb, s->stream));
   {
@@ -1650,8 +1679,10 @@ int hpt_run_batch(hpt_sim* const* sims, int32_t n, const int32_t* nsteps, hpt_me
       if (sims[j] == sims[i]) return HPT_EINVAL;
   }
   if (gemm_profile_active()) return HPT_ESTATE;
-  // a pool of host threads, each driving whole runs on their own streams
-  std::atomic<int> next(0), err(0);
+  // a pool of host threads, each driving whole runs on their own streams;
+  // HPT_BATCH_PROGRESS set: one stderr line as each run completes
+  const bool progress = getenv("HPT_BATCH_PROGRESS") != nullptr;
+  std::atomic<int> next(0), err(0), done(0);
   auto worker = [&]() {
     for (;;) {
       const int i = next.fetch_add(1);
@@ -1670,6 +1701,10 @@ int hpt_run_batch(hpt_sim* const* sims, int32_t n, const int32_t* nsteps, hpt_me
         int z = 0;
         err.compare_exchange_strong(z, (int)HPT_EHIP);
         return;
+      }
+      if (progress) {
+        fprintf(stderr, "[batch] run %d done (%d layers), %d of %d\n", i, nsteps[i], done.fetch_add(1) + 1, n);
+        fflush(stderr);
       }
     }
   };

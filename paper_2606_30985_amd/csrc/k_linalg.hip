@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void pseudo_sqrt_kernel(const PsqJob* jobs, do
 
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void householder_kernel(const QrJob<T>* jobs) {
+__global__ __launch_bounds__(1024) void householder_kernel(const QrJob<T>* jobs) {
   const QrJob<T> job = jobs[blockIdx.x];
   if (gated_out(job.gate, job.gate_zero)) return;
   const int m = job.m, n = job.n, k = m < n ? m : n;
@@ -194,6 +194,8 @@ __global__ __launch_bounds__(256) void householder_kernel(const QrJob<T>* jobs) 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   __shared__ double sh[16];
   __shared__ double s_beta[1024];   // min(m, n) <= 1024 enforced by the caller
+  constexpr int VMAX = 4096;        // reflectors of up to this length are staged in LDS
+  __shared__ double s_v[VMAX];
   double* tau = job.tau;
 
   for (int j = 0; j < k; ++j) {
@@ -224,15 +226,26 @@ __global__ __launch_bounds__(256) void householder_kernel(const QrJob<T>* jobs) 
       A[j + j * lda] = (T)beta;
     }
     __syncthreads();
+    const bool staged = m - j - 1 <= VMAX;
+    if (t != 0.0 && staged)
+      for (int i = j + 1 + tid; i < m; i += blockDim.x) s_v[i - j - 1] = (double)A[i + j * lda];
+    __syncthreads();
     if (t != 0.0) {
+      // one wave per trailing column
       for (int c = j + 1 + wave; c < n; c += nw) {
         double w = 0.0;
-        for (int i = j + 1 + lane; i < m; i += 64) w += (double)A[i + j * lda] * (double)A[i + c * lda];
+        if (staged)
+          for (int i = j + 1 + lane; i < m; i += 64) w += s_v[i - j - 1] * (double)A[i + c * lda];
+        else
+          for (int i = j + 1 + lane; i < m; i += 64) w += (double)A[i + j * lda] * (double)A[i + c * lda];
         w = wave_sum(w) + (double)A[j + c * lda];
         w *= t;
         if (lane == 0) A[j + c * lda] = (T)((double)A[j + c * lda] - w);
-        for (int i = j + 1 + lane; i < m; i += 64)
-          A[i + c * lda] = (T)((double)A[i + c * lda] - (double)A[i + j * lda] * w);
+        if (staged)
+          for (int i = j + 1 + lane; i < m; i += 64) A[i + c * lda] = (T)((double)A[i + c * lda] - s_v[i - j - 1] * w);
+        else
+          for (int i = j + 1 + lane; i < m; i += 64)
+            A[i + c * lda] = (T)((double)A[i + c * lda] - (double)A[i + j * lda] * w);
       }
     }
     __syncthreads();
@@ -832,7 +845,7 @@ int launch_pseudo_sqrt(const PsqJob* jobs, int njobs, double eps_pinv, hipStream
 template <typename T>
 int launch_householder(const QrJob<T>* jobs, int njobs, hipStream_t s) {
   if (njobs <= 0) return 0;
-  hipLaunchKernelGGL(householder_kernel<T>, dim3(njobs), dim3(256), 0, s, jobs);
+  hipLaunchKernelGGL(householder_kernel<T>, dim3(njobs), dim3(1024), 0, s, jobs);
   HPT_LAUNCH_CHECK("householder_kernel");
   return 0;
 }

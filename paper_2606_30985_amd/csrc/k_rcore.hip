@@ -82,6 +82,43 @@ __global__ __launch_bounds__(256) void kron_gram_kernel(BondCore* bonds, GateFac
   }
 }
 
+__global__ __launch_bounds__(256) void precond_prep_kernel(BondCore* bonds) {
+  BondCore& bc = bonds[blockIdx.x];
+  const int q0 = bc.q[0], q1 = bc.q[1];
+  const int m = q0 > q1 ? q0 : q1, n = q0 < q1 ? q0 : q1;
+  const int ld = bc.ldG;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += blockDim.x) {
+    const int i = (int)(idx % n), j = (int)(idx / n);
+    bc.pq[1][i + (int64_t)j * ld] = bc.pq[0][j + (int64_t)i * ld];   // H = R^T
+  }
+  for (int64_t idx = threadIdx.x; idx < (int64_t)m * n; idx += blockDim.x) {
+    const int i = (int)(idx % m), j = (int)(idx / m);
+    bc.pq[2][i + (int64_t)j * ld] = bc.G[i + (int64_t)j * ld];       // Q
+  }
+}
+
+// one wave per column p: sigma_p = |H_out[:, p]|, pq[0][:, p] = V_H[:, p] sigma_p,
+// V[:, p] = H_out[:, p] / sigma_p (0 for a zero column)
+__global__ __launch_bounds__(1024) void precond_finish_kernel(BondCore* bonds) {
+  BondCore& bc = bonds[blockIdx.x];
+  const int q0 = bc.q[0], q1 = bc.q[1];
+  const int n = q0 < q1 ? q0 : q1;
+  const int ld = bc.ldG;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int p = wave; p < n; p += nw) {
+    const double* h = bc.pq[1] + (int64_t)p * ld;
+    double a = 0.0;
+    for (int i = lane; i < n; i += 64) a += h[i] * h[i];
+    a = wave_sum(a);
+    const double sg = sqrt(a);
+    const double inv = sg > 0.0 ? 1.0 / sg : 0.0;
+    for (int i = lane; i < n; i += 64) {
+      bc.pq[0][i + (int64_t)p * ld] = bc.pq[3][i + (int64_t)p * ld] * sg;
+      bc.V[i + (int64_t)p * ld] = h[i] * inv;
+    }
+  }
+}
+
 __global__ __launch_bounds__(1024) void select_kernel(BondCore* bonds) {
   BondCore& bc = bonds[blockIdx.x];
   __shared__ double sh[16];
@@ -213,6 +250,18 @@ int launch_rcore_kron_gram(BondCore* bonds, int nb, const GateFactors& g, hipStr
   if (nb <= 0) return 0;
   hipLaunchKernelGGL(kron_gram_kernel, dim3(nb, 2, 32), dim3(256), 0, s, bonds, g);
   HPT_LAUNCH_CHECK("kron_gram_kernel");
+  return 0;
+}
+int launch_rcore_precond_prep(BondCore* bonds, int nb, hipStream_t s) {
+  if (nb <= 0) return 0;
+  hipLaunchKernelGGL(precond_prep_kernel, dim3(nb), dim3(256), 0, s, bonds);
+  HPT_LAUNCH_CHECK("precond_prep_kernel");
+  return 0;
+}
+int launch_rcore_precond_finish(BondCore* bonds, int nb, hipStream_t s) {
+  if (nb <= 0) return 0;
+  hipLaunchKernelGGL(precond_finish_kernel, dim3(nb), dim3(1024), 0, s, bonds);
+  HPT_LAUNCH_CHECK("precond_finish_kernel");
   return 0;
 }
 int launch_rcore_select(BondCore* bonds, int nb, hipStream_t s) {

@@ -36,6 +36,7 @@ struct BondCore {
   double* msg[2];         // gauge message slots of this bond (chi_new x chi_new)
   double* lam;            // lambda out (chi_max)
   double* qs[2][8];       // float64 scratch of the CholeskyQR2 of B_i (4 chi_max x 4 chi_max each)
+  double* pq[4];          // preconditioned core SVD: R, H = R^T, copy of Q, V of H (ld ldG each)
   // outputs
   int chi_new;
   int n4;                 // 4 * chi_new
@@ -56,6 +57,14 @@ int launch_rcore_build_B(BondCore* bonds, int nb, const GateFactors& g, hipStrea
 // Gram B_i^T B_i of the gated blocks (bqr[i] == 0) from R_i^T R_i in qs[i][5]
 // into qs[i][0]
 int launch_rcore_kron_gram(BondCore* bonds, int nb, const GateFactors& g, hipStream_t s);
+// Preconditioned SVD of the core G (m x n, m >= n, ld ldG), after its
+// Householder QR G = Q R (Q explicit in G, R in pq[0]): prep sets pq[1] = R^T
+// and pq[2] = Q; the one-sided Jacobi then runs on R^T (pq[1], right vectors
+// into pq[3]); finish rescales so that G = (Q V_H) diag(s) U_H^T reads as the
+// plain SVD's output: pq[0] = V_H diag(sigma) (then G = pq[2] pq[0] by a GEMM)
+// and V = H_out diag(1 / sigma).
+int launch_rcore_precond_prep(BondCore* bonds, int nb, hipStream_t s);
+int launch_rcore_precond_finish(BondCore* bonds, int nb, hipStream_t s);
 int launch_rcore_select(BondCore* bonds, int nb, hipStream_t s);
 int launch_rcore_rearrange(BondCore* bonds, int nb, hipStream_t s);
 int launch_rcore_signs(BondCore* bonds, int nb, hipStream_t s);

@@ -1,0 +1,36 @@
+"""Host-only checks of bench.py: the multi-GPU refusal and the counter-based
+traffic lookup (reported only while the kernel source matches the hash
+recorded with the counters)."""
+
+import os
+import shutil
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
+
+
+def test_traffic_ratio_follows_the_kernel_source(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.traffic_ratio("unknown") is None
+    r = bench.traffic_ratio("mode")
+    if r is None:
+        import pytest
+        pytest.skip("the kernel source changed since the counters were taken")
+    assert 1.0 <= r < 3.0
+    # a copy of the tree whose kernel source differs: no traffic figure
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "paper_2606_30985_amd" / "csrc").mkdir(parents=True)
+    shutil.copy(os.path.join(ROOT, "profiles", "mode_product_kernel_10x10_chi100_pmc.md"), tmp_path / "profiles")
+    src = open(os.path.join(ROOT, "paper_2606_30985_amd", "csrc", "k_gemm.hip")).read()
+    (tmp_path / "paper_2606_30985_amd" / "csrc" / "k_gemm.hip").write_text(src + "\n// changed\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.traffic_ratio("mode") is None
