@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 KERNEL_NAMES = {"gemm": "gemm_pipe_kernel (tiled MFMA GEMM)",
-                "gram64": "gemm_pipe_kernel<float, double> (float64-accumulated Gram)",
+                "gram64": "gram64_kernel (float64-accumulated Gram, MFMA f64)",
                 "mode": "mode_product_kernel (MFMA mode product, factor in LDS)",
                 "leggram": "leg_gram_kernel (MFMA leg Gram of the gauge BP, with its partial sum)"}
 

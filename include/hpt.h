@@ -217,8 +217,8 @@ const char* hpt_last_hip_error(void);
  * out4 = {launches, total milliseconds, algorithmic flops (2 M N K per
  * product, half for a symmetric Gram), algorithmic bytes (operands read once,
  * result written once)} for one kernel kind: HPT_PROF_GEMM (gemm_pipe_kernel:
- * general tiled GEMM), HPT_PROF_GRAM64 (the same kernel with float64
- * products and accumulation of float32 data: CholeskyQR Grams),
+ * general tiled GEMM), HPT_PROF_GRAM64 (gram64_kernel: float64 products
+ * and accumulation of float32 data, the CholeskyQR Grams),
  * HPT_PROF_MODE (mode_product_kernel: float32 mode products with the factor
  * resident in LDS), HPT_PROF_LEGGRAM (leg_gram_kernel: float32 leg Grams of
  * the gauge BP, with their partial-sum pass), or -1 for all of them.  hpt_profile_gemm_read(out4) is

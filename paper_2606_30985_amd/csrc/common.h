@@ -54,7 +54,7 @@ template <typename T>
 int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s);
 
 // process-wide event timing of the contraction launches; kind 0 gemm_pipe_kernel,
-// 1 its float64-accumulated Gram, 2 mode_product_kernel, 3 leg_gram_kernel, -1 all
+// 1 the float64-accumulated Gram of float data, 2 mode_product_kernel, 3 leg_gram_kernel, -1 all
 int gemm_profile(int enable);
 int gemm_profile_read(int kind, double* out4);
 int gemm_profile_active();

@@ -10,6 +10,7 @@
 // can be split across workgroups; partial tiles are then summed in float64
 // by a second, deterministic kernel.
 #include <cstdlib>
+#include <type_traits>
 
 #include "common.h"
 
@@ -187,6 +188,136 @@ __global__ __launch_bounds__(256) void gemm_pipe_kernel(GemmDesc<T> d, int tiles
         const int gj = col0 + wc * WT + bj * 16 + cloc;
         if (gi >= d.M || gj >= d.N) continue;
         put<T>(d, z, gi, gj, (double)acc[bi][bj][e], splits, split, part);
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Gram G = X^T X of a float32 matrix X (m x n, column-major, leading dimension
+// ldx) with float64 products and sums (the Gram that feeds CholeskyQR2 in the
+// float32 form).  Upper-triangular 64 x 64 tiles, four waves of 2 x 2 f64
+// 16x16x4 MFMA blocks each; depth-16 chunks of rows of X are fetched as one
+// float4 per thread (128-byte column segments per 8 lanes), kept as float in
+// double-buffered LDS rows of stride 80 (16 mod 64 banks: the four k-rows an
+// MFMA operand read touches land on disjoint banks) and widened to double on
+// the way into the MFMA.  A diagonal tile reads its column block once and uses
+// it for both operands.  16 x 16 blocks that lie past n or strictly below the
+// diagonal issue no MFMA.  The rows of X are split over blockIdx.y; every
+// split writes its partial tile (upper blocks) for a fixed-order reduction.
+constexpr int G64_TK = 16, G64_SP = 80;
+
+template <bool VEC>
+__device__ inline float4 g64_load(const float* p, bool valid, bool full, int rem) {
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (!valid) return v;
+  if (VEC && full) return *(const float4*)p;
+  if (full || rem > 0) v.x = p[0];
+  if (full || rem > 1) v.y = p[1];
+  if (full || rem > 2) v.z = p[2];
+  if (full || rem > 3) v.w = p[3];
+  return v;
+}
+
+// VEC: ldx % 4 == 0 and X 16-byte aligned (float4 loads of whole chunks)
+template <bool VEC>
+__global__ __launch_bounds__(256) void gram64_kernel(const float* __restrict__ X, int64_t ldx, int m, int n,
+                                                     int splits, int chunks, double* __restrict__ part) {
+  constexpr int BT = 64, TK = G64_TK, SP = G64_SP;
+  constexpr int KQ = TK / 4, CPP = 256 / KQ;   // 4 threads per column, all 64 columns in one pass
+  static_assert(CPP == BT, "one float4 per thread and operand");
+  __shared__ float As[2][TK][SP];
+  __shared__ float Bs[2][TK][SP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wr = wave >> 1, wc = wave & 1;
+  // upper-triangular tile (tm <= tn), column by column
+  int t = blockIdx.x, tn = 0;
+  while (t > tn) { t -= tn + 1; ++tn; }
+  const int tm = t;
+  const bool diag = tm == tn;
+  const int row0 = tm * BT, col0 = tn * BT;
+  // 16-row blocks of G this wave computes: inside n and on or above the diagonal
+  const int nb = (n + 15) / 16;
+  bool run[2][2];
+  bool active = false;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int rb = (row0 + wr * 32) / 16 + i, cb = (col0 + wc * 32) / 16 + j;
+      run[i][j] = rb < nb && cb < nb && rb <= cb;
+      active = active || run[i][j];
+    }
+  const int split = blockIdx.y;
+  const int per = (chunks + splits - 1) / splits;
+  const int c_begin = split * per;
+  const int c_end = c_begin + per < chunks ? c_begin + per : chunks;
+  const int kq = tid % KQ, cl = tid / KQ;
+  const bool va = row0 + cl < n, vb = col0 + cl < n;
+  const float* pa = X + (int64_t)(va ? row0 + cl : 0) * ldx + 4 * kq;
+  const float* pb = X + (int64_t)(vb ? col0 + cl : 0) * ldx + 4 * kq;
+  d4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0.0;
+  float4 ra, rb;
+  auto load = [&](int c) {
+    const int k0 = c * TK;
+    const bool full = k0 + TK <= m;
+    const int rem = m - k0 - 4 * kq;
+    ra = g64_load<VEC>(pa + k0, va, full, rem);
+    if (!diag) rb = g64_load<VEC>(pb + k0, vb, full, rem);
+  };
+  auto store = [&](int buf) {
+    As[buf][4 * kq + 0][cl] = ra.x; As[buf][4 * kq + 1][cl] = ra.y;
+    As[buf][4 * kq + 2][cl] = ra.z; As[buf][4 * kq + 3][cl] = ra.w;
+    if (!diag) {
+      Bs[buf][4 * kq + 0][cl] = rb.x; Bs[buf][4 * kq + 1][cl] = rb.y;
+      Bs[buf][4 * kq + 2][cl] = rb.z; Bs[buf][4 * kq + 3][cl] = rb.w;
+    }
+  };
+  if (c_begin < c_end) {
+    load(c_begin);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int c = c_begin; c < c_end; ++c) {
+      const bool more = c + 1 < c_end;
+      if (more) load(c + 1);
+      if (active) {
+        const float (*Bsrc)[SP] = diag ? As[buf] : Bs[buf];
+#pragma unroll
+        for (int kk = 0; kk < TK / 4; ++kk) {
+          const int kr = kk * 4 + (lane >> 4);
+          double a[2], b[2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) a[i] = (double)As[buf][kr][wr * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) b[j] = (double)Bsrc[kr][wc * 32 + j * 16 + (lane & 15)];
+          // B fragment first: register e of block (i, j) is G[row lane%16, col lane/16 + 4 e]
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              if (run[i][j]) acc[i][j] = mfma_op(b[j], a[i], acc[i][j]);
+        }
+      }
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+  if (!active) return;
+  double* out = part + (int64_t)split * n * n;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gi = row0 + wr * 32 + i * 16 + (lane & 15);
+        const int gj = col0 + wc * 32 + j * 16 + (lane >> 4) + 4 * e;
+        if (run[i][j] && gi < n && gj < n && gi <= gj) out[(int64_t)gj * n + gi] = acc[i][j][e];
       }
 }
 
@@ -565,7 +696,7 @@ __global__ __launch_bounds__(1024) void gemm_reduce_kernel(GemmDesc<T> d, int sp
 // Optional timing of every contraction launch with HIP events on the launch
 // stream (process-wide), per kernel kind, for the roofline report.
 constexpr int PROF_CAP = 4096;
-constexpr int PROF_KINDS = 4;   // 0 gemm_pipe_kernel, 1 its float64-accumulated Gram, 2 mode_product_kernel, 3 leg_gram_kernel
+constexpr int PROF_KINDS = 4;   // 0 gemm_pipe_kernel, 1 float64-accumulated Gram (gram64_kernel), 2 mode_product_kernel, 3 leg_gram_kernel
 struct GemmProfile {
   int on = 0;
   int n = 0;
@@ -647,6 +778,47 @@ int gemm_profile_read(int kind, double* out4) {
   return 0;
 }
 
+namespace {
+// the float64-accumulated Gram G = X^T X of a float32 X, written whole
+// (mirrored) into a float64 C, is served by gram64_kernel
+bool gram64_eligible(const GemmDesc<float>& d, int64_t part_cap) {
+  return d.acc64 && d.sym && d.R == 1 && d.Z == 1 && d.tA && !d.tB && d.A == d.B && d.lda == d.ldb &&
+         d.c_double && d.M == d.N && d.K <= 0x7fffffff - G64_TK && (int64_t)d.M * d.M <= part_cap;
+}
+
+int gram64(const GemmDesc<float>& d, double* part, int64_t part_cap, hipStream_t s) {
+  const int n = d.M, m = d.K;
+  const int tiles_m = (int)ceil_div(n, 64);
+  const int64_t tiles = (int64_t)tiles_m * (tiles_m + 1) / 2;
+  const int chunks = (int)ceil_div(m, G64_TK);
+  // split the rows of X while the grid stays within ~4096 workgroups, each
+  // split keeps at least 16 chunks, and the partials fit the scratch
+  int splits = 1;
+  while (splits < 128 && tiles * splits * 2 <= 4096 && chunks / (splits * 2) >= 16 &&
+         (int64_t)splits * 2 * n * n <= part_cap)
+    splits *= 2;
+  const bool vec = d.lda % 4 == 0 && ((uintptr_t)d.A & 15) == 0;
+  RC_PROF(prof_begin(s));
+  if (vec)
+    hipLaunchKernelGGL(gram64_kernel<true>, dim3((unsigned)tiles, (unsigned)splits), dim3(256), 0, s, d.A, d.lda, m,
+                       n, splits, chunks, part);
+  else
+    hipLaunchKernelGGL(gram64_kernel<false>, dim3((unsigned)tiles, (unsigned)splits), dim3(256), 0, s, d.A, d.lda,
+                       m, n, splits, chunks, part);
+  HPT_LAUNCH_CHECK("gram64_kernel");
+  {
+    const double N = n, K = m;
+    // algorithmic: half the products of a full n x n product; X read once, G written once
+    RC_PROF(prof_end(s, 1, N * N * K, 4.0 * K * N + 8.0 * N * N));
+  }
+  const int64_t blocks = ceil_div((int64_t)n * n, 64);
+  hipLaunchKernelGGL(gemm_reduce_kernel<float>, dim3((unsigned)blocks), dim3(1024), 0, s, d, splits,
+                     (const double*)part);
+  HPT_LAUNCH_CHECK("gemm_reduce_kernel");
+  return 0;
+}
+}  // namespace
+
 template <typename T>
 int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.Z <= 0) return 0;
@@ -656,6 +828,8 @@ int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
     const char* e = getenv("HPT_GEMM_TILE");
     return e ? atoi(e) : 0;
   }();
+  if constexpr (std::is_same<T, float>::value)
+    if (gram64_eligible(d, part_cap)) return gram64(d, part, part_cap, s);
   const bool big = !d.acc64 && forced == 128;
   const int tile = big ? 128 : 64;
   const int tiles_m = (int)ceil_div(d.M, tile), tiles_n = (int)ceil_div(d.N, tile);
