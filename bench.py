@@ -24,11 +24,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
+FORM_NAMES = {"fp32": "FP32-MFMA form", "bf16x6": "FP32 form with split-bf16 (x6) GEMMs", "fp64": "FP64 plain form"}
 KERNEL_NAMES = {"gemm": "gemm_pipe_kernel (tiled MFMA GEMM)",
                 "gram64": "gram64_kernel (float64-accumulated Gram, MFMA f64)",
                 "mode": "mode_product_kernel (MFMA mode product, factor in LDS)",
-                "leggram": "leg_gram_kernel (MFMA leg Gram of the gauge BP, with its partial sum)"}
+                "leggram": "leg_gram_kernel (MFMA leg Gram of the gauge BP, with its partial sum)",
+                "bsplit": "bsplit_gemm_kernel (six bf16 MFMA products of split float32 operands)"}
 
 
 def parse():
@@ -36,7 +38,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=28)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x6", "fp64"])
     ap.add_argument("--L", type=int, default=10)
     ap.add_argument("--chi", type=int, default=100)
     ap.add_argument("--dt", type=float, default=0.05)
@@ -238,8 +240,14 @@ def main():
     ratio = traffic_ratio(dom)
     achieved = prof["flops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else 0.0
     # float64 products (the Gram of float32 data, or every product of the
-    # float64 form) run on the FP64 MFMA
-    peak = PEAK_TFLOPS["fp64" if (dom == "gram64" or args.precision == "fp64") else "fp32"]
+    # float64 form) run on the FP64 MFMA; the split-bf16 products on the bf16
+    # MFMA, each of their algorithmic flops costing six bf16 flops
+    if dom == "gram64" or args.precision == "fp64":
+        peak = PEAK_TFLOPS["fp64"]
+    elif dom == "bsplit":
+        peak = PEAK_TFLOPS["bf16"] / 6.0
+    else:
+        peak = PEAK_TFLOPS["fp32"]
     out = {
         "metric": "Trotter layers/sec at 10x10 chi=100 (|dC(t)| vs FP64 oracle); bond updates/sec",
         "value": value,
@@ -251,10 +259,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic (deterministic initial operator Z_c, no dataset)",
         "config": {"workload": f"{L}x{L} TFIM Heisenberg Z_c(t), chi_max={chi}, dt={args.dt}, J=h=1, "
-                               f"{'FP32-MFMA form' if args.precision == 'fp32' else 'FP64 plain form'}, "
+                               f"{FORM_NAMES[args.precision]}, "
                                f"gauge BP tol {args.bp_tol} max {args.bp_max_sweeps} sweeps, damping 0.5, "
                                f"{args.bp_init} init; measurement BP tol {args.meas_tol} max "
                                f"{args.meas_max_sweeps} sweeps; layers {args.warmup + 1}..{args.warmup + args.steps}",

@@ -52,6 +52,10 @@ extern "C" {
 #define HPT_FP64       0  /* plain form: every step in float64 */
 #define HPT_FP32_MFMA  1  /* float32 site tensors and MFMA contractions; float64
                              Cholesky, R-core SVD, eigensolver, BP normalisation, Bethe sum */
+#define HPT_FP32_BF16X6 2 /* HPT_FP32_MFMA with the plain float32 products (the reconstruction
+                             X (R^-1 M') of every gate) taken as six bf16 MFMA products of the
+                             round-to-nearest three-way bf16 split of each operand, accumulated
+                             in float32 (BF16 split precision); everything else as HPT_FP32_MFMA */
 
 /* QR strategy (Sec. "Adaptive QR Decomposition") */
 #define HPT_QR_ADAPTIVE    0  /* CholeskyQR2 for tall blocks, Householder otherwise or on failure */
@@ -80,7 +84,7 @@ typedef struct {
   double  J, h, dt;        /* coupling, field, time step (dt != 0) */
   int32_t chi_max;         /* bond-dimension cap, >= 1 */
   int32_t cx, cy;          /* observable site; -1,-1 -> ((Lx-1)/2, (Ly-1)/2) */
-  int32_t precision;       /* HPT_FP64 | HPT_FP32_MFMA */
+  int32_t precision;       /* HPT_FP64 | HPT_FP32_MFMA | HPT_FP32_BF16X6 */
   int32_t qr_mode;         /* HPT_QR_ADAPTIVE | HPT_QR_HOUSEHOLDER */
   int32_t chol_min_ratio;  /* CholeskyQR2 needs rows >= chol_min_ratio * cols (default 2) */
   int32_t chol_min_cols;   /* ... and cols >= chol_min_cols (default 16); the paper's
@@ -221,13 +225,16 @@ const char* hpt_last_hip_error(void);
  * and accumulation of float32 data, the CholeskyQR Grams),
  * HPT_PROF_MODE (mode_product_kernel: float32 mode products with the factor
  * resident in LDS), HPT_PROF_LEGGRAM (leg_gram_kernel: float32 leg Grams of
- * the gauge BP, with their partial-sum pass), or -1 for all of them.  hpt_profile_gemm_read(out4) is
+ * the gauge BP, with their partial-sum pass), HPT_PROF_BSPLIT
+ * (bsplit_gemm_kernel: the split-bf16 products of HPT_FP32_BF16X6), or -1
+ * for all of them.  hpt_profile_gemm_read(out4) is
  * hpt_profile_read(-1, out4).  For the roofline report of the contractions.
  * Returns HPT_EINVAL for a null out4 or an unknown kind. */
 #define HPT_PROF_GEMM 0
 #define HPT_PROF_GRAM64 1
 #define HPT_PROF_MODE 2
 #define HPT_PROF_LEGGRAM 3
+#define HPT_PROF_BSPLIT 4
 int hpt_profile_gemm(int32_t enable);
 int hpt_profile_gemm_read(double* out4);
 int hpt_profile_read(int32_t kind, double* out4);

@@ -10,6 +10,7 @@ namespace hpt {
 
 typedef __attribute__((ext_vector_type(4))) double d4;
 typedef __attribute__((ext_vector_type(4))) float f4;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf8;
 
 // Error handling: every HIP call in host code goes through HPT_HIP.
 void set_hip_error(hipError_t e, const char* what);
@@ -49,6 +50,8 @@ struct GemmDesc {
   int sym;   // op(B) = op(A)^T and M == N: only tiles on or above the diagonal
              // are computed, the result is mirrored (a SYRK)
   int acc64; // float inputs multiplied and accumulated in float64 (f64 MFMA)
+  int bsplit; // float inputs: six bf16 MFMA products of the three-way bf16 split
+              // of each operand, float32 accumulation (plain products only)
 };
 template <typename T>
 int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s);

@@ -80,6 +80,7 @@ struct hpt_sim {
   hpt_config cfg;
   int N, nb, centre, chi_max;
   bool fp32;
+  bool bsplit;   // the split-bf16 form of the float32 GEMMs
   int elem;
   std::vector<hpt::SiteInfo> sites;
   std::vector<hpt::BondInfo> bonds;

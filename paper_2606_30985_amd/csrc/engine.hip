@@ -83,7 +83,7 @@ int validate(const hpt_config* c) {
   if (c->chi_max < 1 || c->chi_max > 256) return HPT_EINVAL;
   const int cx = c->cx < 0 ? (c->Lx - 1) / 2 : c->cx, cy = c->cy < 0 ? (c->Ly - 1) / 2 : c->cy;
   if (cx >= c->Lx || cy >= c->Ly) return HPT_EINVAL;
-  if (c->precision != HPT_FP64 && c->precision != HPT_FP32_MFMA) return HPT_EINVAL;
+  if (c->precision != HPT_FP64 && c->precision != HPT_FP32_MFMA && c->precision != HPT_FP32_BF16X6) return HPT_EINVAL;
   if (c->qr_mode != HPT_QR_ADAPTIVE && c->qr_mode != HPT_QR_HOUSEHOLDER) return HPT_EINVAL;
   if (c->chol_min_ratio < 1 || c->chol_min_cols < 1) return HPT_EINVAL;
   if (!(c->eps_cut < 1.0) || !(c->eps_pinv >= 0.0)) return HPT_EINVAL;
@@ -195,7 +195,7 @@ void make_carve(const hpt_config& c, Carve& cv) {
   std::vector<SiteInfo> sites;
   std::vector<BondInfo> bonds;
   build_topology(c, sites, bonds);
-  const bool fp32 = c.precision == HPT_FP32_MFMA;
+  const bool fp32 = c.precision != HPT_FP64;
   const uint64_t E = fp32 ? 4 : 8;
   const int C = c.chi_max;
   const int N = (int)sites.size(), nb = (int)bonds.size();
@@ -354,6 +354,7 @@ int matmul(hpt_sim* s, int64_t m, int64_t n, int64_t k, const T* A, int64_t lda,
   d.B = B; d.ldb = ldb; d.tB = tB;
   d.C = C; d.ldc = ldc; d.c_double = c_double;
   d.alpha = 1.0; d.beta = 0.0;
+  d.bsplit = s->bsplit;
   KR(gemm<T>(d, s->part, s->cv.part_cap, s->stream));
   return 0;
 }
@@ -1544,7 +1545,7 @@ int hpt_state_bytes(const hpt_config* cfg, uint64_t* bytes) {
   std::vector<SiteInfo> sites;
   std::vector<BondInfo> bonds;
   build_topology(*cfg, sites, bonds);
-  const uint64_t E = cfg->precision == HPT_FP32_MFMA ? 4 : 8;
+  const uint64_t E = cfg->precision != HPT_FP64 ? 4 : 8;
   uint64_t tot = 0;
   for (auto& s : sites) tot += 4ull * (uint64_t)ipow(cfg->chi_max, s.deg) * E;
   *bytes = tot;
@@ -1559,7 +1560,8 @@ int hpt_create(const hpt_config* cfg, void* arena, uint64_t arena_bytes, void* h
   hpt_sim* s = new (std::nothrow) hpt_sim();
   if (!s) return HPT_ENOMEM;
   s->cfg = *cfg;
-  s->fp32 = cfg->precision == HPT_FP32_MFMA;
+  s->fp32 = cfg->precision != HPT_FP64;
+  s->bsplit = cfg->precision == HPT_FP32_BF16X6;
   s->elem = s->fp32 ? 4 : 8;
   s->chi_max = cfg->chi_max;
   build_topology(*cfg, s->sites, s->bonds);
@@ -1865,7 +1867,7 @@ int hpt_profile_gemm(int32_t enable) {
 int hpt_profile_gemm_read(double* out4) { return hpt_profile_read(-1, out4); }
 
 int hpt_profile_read(int32_t kind, double* out4) {
-  if (!out4 || kind < -1 || kind > 3) return HPT_EINVAL;
+  if (!out4 || kind < -1 || kind > 4) return HPT_EINVAL;
   const int r = gemm_profile_read(kind, out4);
   return r == 0 ? HPT_OK : HPT_EHIP;
 }

@@ -322,6 +322,141 @@ __global__ __launch_bounds__(256) void gram64_kernel(const float* __restrict__ X
 }
 
 // ---------------------------------------------------------------------------
+// Split-bf16 GEMM C = A B for float32 A (M x K) and B (K x N), column-major,
+// float32 C.  Every operand element x is split to nearest into three bf16
+// parts, x = h + m + l (h = bf16(x), m = bf16(x - h), l = x - h - m, which
+// has at most 8 significant bits and is exact in bf16).  The product keeps
+// the six terms down to relative order 2^-16, hh + hm + mh + mm + hl + lh;
+// the dropped ml + lm + ll are below 2^-23 of |a b|, so the result carries
+// float32-level error at the bf16 MFMA rate (gfx950 v_mfma_f32_16x16x32_bf16,
+// 8 k-values per lane and operand).  Tile 128 x 80: four waves of 32 rows x
+// 80 columns (2 x 5 blocks of 16 x 16), k-chunks of 32 split while staged
+// into LDS (three bf16 planes per operand, rows of 80 bytes: 16-lane
+// ds_read_b128 groups hit distinct banks).  Operands go into the MFMA with B
+// first, so the 16 lanes of a result register run along C's rows.  The tiles
+// of one XCD (workgroup id mod 8) form a contiguous range, the column tiles
+// of a row strip adjacent, so a strip of A is fetched from HBM once.
+constexpr int BS_BM = 128, BS_BN = 80, BS_KC = 32, BS_RS = 40;   // BS_RS: LDS row stride in bf16
+
+__device__ inline void bsplit3(float x, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)x;
+  const float r = x - (float)h;
+  m = (__bf16)r;
+  l = (__bf16)(r - (float)m);
+}
+
+__device__ inline void bsplit_put(const float* v, __bf16* h0, __bf16* m0, __bf16* l0) {
+  bf8 h, m, l;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    __bf16 a, b, c;
+    bsplit3(v[e], a, b, c);
+    h[e] = a; m[e] = b; l[e] = c;
+  }
+  *(bf8*)h0 = h;
+  *(bf8*)m0 = m;
+  *(bf8*)l0 = l;
+}
+
+__global__ __launch_bounds__(256) void bsplit_gemm_kernel(const float* __restrict__ A, int64_t lda,
+                                                          const float* __restrict__ B, int64_t ldb,
+                                                          float* __restrict__ C, int64_t ldc, int M, int N, int K,
+                                                          int ntn, int64_t total, int64_t per_xcd) {
+  constexpr int BM = BS_BM, BN = BS_BN, KC = BS_KC, RS = BS_RS;
+  __shared__ __attribute__((aligned(16))) __bf16 As[3][BM * RS];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[3][BN * RS];
+  const int64_t T = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (T >= total) return;
+  const int row0 = (int)(T / ntn) * BM, col0 = (int)(T % ntn) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // A staging: row ar of the tile, k-groups (8 k each) akg and akg + 2
+  const int ar = tid & 127, akg = tid >> 7;
+  const bool a_ok = row0 + ar < M;
+  const float* Ap = A + (a_ok ? row0 + ar : 0);
+  // B staging: units tid and tid + 256 (< 320) = (column u % 80, k-group u / 80)
+  const int u1 = tid + 256;
+  const bool u1_ok = u1 < BN * 4;
+  const int bc0 = tid % BN, bk0 = tid / BN, bc1 = u1 % BN, bk1 = u1 / BN;
+  const bool b0_ok = col0 + bc0 < N, b1_ok = u1_ok && col0 + bc1 < N;
+  const float* Bp0 = B + (int64_t)(b0_ok ? col0 + bc0 : 0) * ldb;
+  const float* Bp1 = B + (int64_t)(b1_ok ? col0 + bc1 : 0) * ldb;
+  float ra[16], rb[16];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = k0 + 8 * (akg + 2 * g) + e;
+        ra[8 * g + e] = (a_ok && k < K) ? Ap[(int64_t)k * lda] : 0.f;
+      }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k0e = k0 + 8 * bk0 + e, k1e = k0 + 8 * bk1 + e;
+      rb[e] = (b0_ok && k0e < K) ? Bp0[k0e] : 0.f;
+      rb[8 + e] = (b1_ok && k1e < K) ? Bp1[k1e] : 0.f;
+    }
+  };
+  f4 acc[2][5];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  const int nchunks = (K + KC - 1) / KC;
+  load(0);
+  for (int c = 0; c < nchunks; ++c) {
+    __syncthreads();   // every wave is done reading the previous chunk
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int off = ar * RS + 8 * (akg + 2 * g);
+      bsplit_put(ra + 8 * g, &As[0][off], &As[1][off], &As[2][off]);
+    }
+    {
+      const int off = bc0 * RS + 8 * bk0;
+      bsplit_put(rb, &Bs[0][off], &Bs[1][off], &Bs[2][off]);
+    }
+    if (u1_ok) {
+      const int off = bc1 * RS + 8 * bk1;
+      bsplit_put(rb + 8, &Bs[0][off], &Bs[1][off], &Bs[2][off]);
+    }
+    __syncthreads();
+    if (c + 1 < nchunks) load((c + 1) * KC);
+    bf8 af[2][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) af[i][p] = *(const bf8*)&As[p][(32 * w + 16 * i + (lane & 15)) * RS + 8 * (lane >> 4)];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      bf8 bf[3];
+#pragma unroll
+      for (int p = 0; p < 3; ++p) bf[p] = *(const bf8*)&Bs[p][(16 * j + (lane & 15)) * RS + 8 * (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        // smallest terms first
+        f4 a = acc[i][j];
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[0], af[i][2], a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[2], af[i][0], a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[1], af[i][1], a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[0], af[i][1], a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[1], af[i][0], a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[0], af[i][0], a, 0, 0, 0);
+        acc[i][j] = a;
+      }
+    }
+  }
+  // register e of block (i, j): C[row 32 w + 16 i + lane % 16, column 16 j + 4 (lane / 16) + e]
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = row0 + 32 * w + 16 * i + (lane & 15), cc = col0 + 16 * j + 4 * (lane >> 4) + e;
+        if (r < M && cc < N) C[r + (int64_t)cc * ldc] = acc[i][j][e];
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Mode products of the float32 form with the n x n factor resident in LDS
 // (n <= 128), persistent workgroups of 4 waves, each wave streaming 16-row
 // (or 16-column) strips of the tensor straight from HBM into MFMA operands.
@@ -696,7 +831,8 @@ __global__ __launch_bounds__(1024) void gemm_reduce_kernel(GemmDesc<T> d, int sp
 // Optional timing of every contraction launch with HIP events on the launch
 // stream (process-wide), per kernel kind, for the roofline report.
 constexpr int PROF_CAP = 4096;
-constexpr int PROF_KINDS = 4;   // 0 gemm_pipe_kernel, 1 float64-accumulated Gram (gram64_kernel), 2 mode_product_kernel, 3 leg_gram_kernel
+constexpr int PROF_KINDS = 5;   // 0 gemm_pipe_kernel, 1 float64-accumulated Gram (gram64_kernel), 2 mode_product_kernel,
+                                 // 3 leg_gram_kernel, 4 split-bf16 GEMM (bsplit_gemm_kernel)
 struct GemmProfile {
   int on = 0;
   int n = 0;
@@ -819,6 +955,29 @@ int gram64(const GemmDesc<float>& d, double* part, int64_t part_cap, hipStream_t
 }
 }  // namespace
 
+namespace {
+// plain float32 products C = A B (no transposes, batches or scaling) in the
+// split-bf16 form
+bool bsplit_eligible(const GemmDesc<float>& d) {
+  return d.bsplit && !d.acc64 && !d.sym && !d.tA && !d.tB && d.R == 1 && d.Z == 1 && !d.c_double &&
+         d.alpha == 1.0 && d.beta == 0.0;
+}
+
+int bsplit_gemm(const GemmDesc<float>& d, hipStream_t s) {
+  const int ntn = (int)ceil_div(d.N, BS_BN);
+  const int64_t total = ceil_div(d.M, BS_BM) * (int64_t)ntn;
+  const int64_t per_xcd = ceil_div(total, 8);
+  if (8 * per_xcd > 0x7fffffff) return -1;
+  RC_PROF(prof_begin(s));
+  hipLaunchKernelGGL(bsplit_gemm_kernel, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, d.A, d.lda, d.B, d.ldb,
+                     (float*)d.C, d.ldc, d.M, d.N, d.K, ntn, total, per_xcd);
+  HPT_LAUNCH_CHECK("bsplit_gemm_kernel");
+  const double M = d.M, N = d.N, K = d.K;
+  RC_PROF(prof_end(s, 4, 2.0 * M * N * K, 4.0 * (M * K + K * N + M * N)));
+  return 0;
+}
+}  // namespace
+
 template <typename T>
 int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.Z <= 0) return 0;
@@ -828,8 +987,10 @@ int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
     const char* e = getenv("HPT_GEMM_TILE");
     return e ? atoi(e) : 0;
   }();
-  if constexpr (std::is_same<T, float>::value)
+  if constexpr (std::is_same<T, float>::value) {
     if (gram64_eligible(d, part_cap)) return gram64(d, part, part_cap, s);
+    if (bsplit_eligible(d)) return bsplit_gemm(d, s);
+  }
   const bool big = !d.acc64 && forced == 128;
   const int tile = big ? 128 : 64;
   const int tiles_m = (int)ceil_div(d.M, tile), tiles_n = (int)ceil_div(d.N, tile);

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhpt.so")
 
 HPT_FP64 = 0
 HPT_FP32_MFMA = 1
+HPT_FP32_BF16X6 = 2
 HPT_QR_ADAPTIVE = 0
 HPT_QR_HOUSEHOLDER = 1
 HPT_BP_UNIFORM = 0
@@ -127,7 +128,7 @@ def profile_gemm(enable=True):
     check(lib.hpt_profile_gemm(1 if enable else 0), "hpt_profile_gemm")
 
 
-PROF_KINDS = {"gemm": 0, "gram64": 1, "mode": 2, "leggram": 3}
+PROF_KINDS = {"gemm": 0, "gram64": 1, "mode": 2, "leggram": 3, "bsplit": 4}
 
 
 def profile_gemm_read(kind=None):
@@ -176,7 +177,7 @@ def make_config(**kw):
     names = {n for n, _ in HptConfig._fields_}
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
-            v = {"fp64": HPT_FP64, "fp32": HPT_FP32_MFMA, "fp32_mfma": HPT_FP32_MFMA}[v]
+            v = {"fp64": HPT_FP64, "fp32": HPT_FP32_MFMA, "fp32_mfma": HPT_FP32_MFMA, "bf16x6": HPT_FP32_BF16X6}[v]
         if k == "qr_mode" and isinstance(v, str):
             v = {"adaptive": HPT_QR_ADAPTIVE, "householder": HPT_QR_HOUSEHOLDER}[v]
         if k == "bp_init" and isinstance(v, str):

@@ -50,7 +50,7 @@ def _paper_state_floats(k, l, chi):
 
 @pytest.mark.parametrize("k,l,chi", [(3, 3, 8), (4, 4, 60), (10, 10, 100), (11, 11, 100), (5, 7, 13)])
 def test_state_term_matches_paper_memory_model(hpt, k, l, chi):
-    for prec, size in ((0, 8), (1, 4)):
+    for prec, size in ((0, 8), (1, 4), (2, 4)):
         c = hpt.make_config(Lx=k, Ly=l, chi_max=chi, precision=prec)
         assert hpt.state_bytes(c) == _paper_state_floats(k, l, chi) * size
 
@@ -66,6 +66,9 @@ def test_required_bytes_fit_the_large_instance(hpt):
     assert b32 < 130e9
     assert b64 < 260e9
     assert b64 > hpt.state_bytes(c64)
+    # the split-bf16 form keeps the float32 layout
+    cs = hpt.make_config(Lx=10, Ly=10, chi_max=100, precision="bf16x6")
+    assert hpt.required_bytes(cs) == b32
 
 
 def test_strerror(hpt):

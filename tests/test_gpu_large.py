@@ -41,9 +41,12 @@ def _run(hpt, precision, steps, **extra):
 
 
 def test_10x10_chi100_fp32_form_against_fp64():
+    # both float32 forms: plain float32 products, and six bf16 products of
+    # split operands (precision "bf16x6"), against one float64 run
     hpt = load_hpt()
     steps = int(os.environ.get("HPT_LARGE_STEPS", "30"))
     r32 = _run(hpt, "fp32", steps)
+    rbs = _run(hpt, "bf16x6", steps)
     # the FP64 reference: same truncation cutoff as the FP32 form (1e-7 s_0),
     # so the comparison isolates the arithmetic; dependent QR columns are
     # deflated below 1e-15 of the largest Gram pivot (singular values below
@@ -51,19 +54,20 @@ def test_10x10_chi100_fp32_form_against_fp64():
     # single-workgroup Householder
     r64 = _run(hpt, "fp64", steps, qr_rank_tol=1e-15, eps_cut=1e-7)
     bad = hpt.FLAGS["BP_NOT_CONVERGED_MEAS"]
-    rows = []
-    for a, b in zip(r32, r64):
-        ok = not (a["flags"] & bad) and not (b["flags"] & bad)
-        rows.append(dict(step=a["step"], t=a["t"], C32=a["C"], C64=b["C"], dC=abs(a["C"] - b["C"]), compared=ok,
-                         meas_sweeps=[a["meas_sweeps"], b["meas_sweeps"]], seconds=[a["seconds"], b["seconds"]]))
-    print("# fp32-vs-fp64 " + json.dumps(rows), file=sys.stderr, flush=True)
-    cmp = [r for r in rows if r["compared"]]
-    assert cmp, "no layer with both measurement BPs converged"
-    # layers up to t = 1.0 (chi below chi_max on most bonds): float32 storage
-    # and the gauge BP's 1e-5 tolerance leave |dC| at the 1e-6 level
-    early = [r for r in cmp if r["t"] <= 1.0 + 1e-12]
-    assert max(r["dC"] for r in early) <= 5e-6
-    assert max(r["dC"] for r in cmp) <= 5e-5
+    for name, rf in (("fp32", r32), ("bf16x6", rbs)):
+        rows = []
+        for a, b in zip(rf, r64):
+            ok = not (a["flags"] & bad) and not (b["flags"] & bad)
+            rows.append(dict(step=a["step"], t=a["t"], C32=a["C"], C64=b["C"], dC=abs(a["C"] - b["C"]), compared=ok,
+                             meas_sweeps=[a["meas_sweeps"], b["meas_sweeps"]], seconds=[a["seconds"], b["seconds"]]))
+        print(f"# {name}-vs-fp64 " + json.dumps(rows), file=sys.stderr, flush=True)
+        cmp = [r for r in rows if r["compared"]]
+        assert cmp, "no layer with both measurement BPs converged"
+        # layers up to t = 1.0 (chi below chi_max on most bonds): float32
+        # storage and the gauge BP's 1e-5 tolerance leave |dC| at the 1e-6 level
+        early = [r for r in cmp if r["t"] <= 1.0 + 1e-12]
+        assert max(r["dC"] for r in early) <= 5e-6, name
+        assert max(r["dC"] for r in cmp) <= 5e-5, name
 
 
 def test_10x10_chi30_fp64_against_oracle():

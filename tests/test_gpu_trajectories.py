@@ -54,7 +54,10 @@ def test_config1_chi20_fp64_vs_golden():
         assert abs(got[k]["C"] - rec["C"]) <= 1e-10, (k, got[k]["C"], rec["C"])
 
 
-def test_config0_fp32_form():
+# "bf16x6": the float32 form with its plain products taken as six bf16 MFMA
+# products of split operands (float32-level rounding), held to the same bounds
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+def test_config0_fp32_form(precision):
     # float32 tensors and MFMA contractions, float64 Cholesky / SVD / BP
     # normalisation / Bethe: |dC| against the float64 oracle stays at the
     # few-1e-7 .. 1e-6 level set by float32 storage of the site tensors
@@ -65,14 +68,15 @@ def test_config0_fp32_form():
     # the FP32 form's default truncation cutoff sits at the float32 noise
     # floor (1e-7 s_0); here the paper's 1e-11 is kept below it to compare
     # the arithmetic alone
-    got = _traj(hpt, cfg, g["nsteps"], precision="fp32", eps_cut=1e-9)
+    got = _traj(hpt, cfg, g["nsteps"], precision=precision, eps_cut=1e-9)
     worst = max(abs(got[k]["C"] - rec["C"]) for k, rec in enumerate(g["records"]))
-    print("fp32 form worst |dC| on 3x3 chi 8:", worst, "per layer:",
+    print(precision, "form worst |dC| on 3x3 chi 8:", worst, "per layer:",
           " ".join(f"{abs(got[k]['C'] - rec['C']):.1e}" for k, rec in enumerate(g["records"])))
     assert worst <= 2e-6
 
 
-def test_config1_chi20_fp32_form():
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+def test_config1_chi20_fp32_form(precision):
     # the float32 form on 4x4 chi 20: |dC| against the float64 oracle, first
     # 30 layers.  Up to t = 0.9 (layer 18) the difference stays at the level
     # set by the float32 gauge BP (converged to 1e-6, its float32 floor, so
@@ -83,9 +87,9 @@ def test_config1_chi20_fp32_form():
     g = _golden("oracle_4x4_chi20")
     cfg = dict(g["config"])
     cfg["bp_tol"] = 1e-6
-    got = _traj(hpt, cfg, 30, precision="fp32")
+    got = _traj(hpt, cfg, 30, precision=precision)
     d = [abs(got[k]["C"] - g["records"][k]["C"]) for k in range(31)]
-    print("fp32 form |dC| on 4x4 chi 20 per layer:", " ".join(f"{x:.1e}" for x in d))
+    print(precision, "form |dC| on 4x4 chi 20 per layer:", " ".join(f"{x:.1e}" for x in d))
     assert max(d[:19]) <= 4e-6
     assert max(d) <= 5e-5
 
