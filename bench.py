@@ -259,7 +259,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x6": "f32 (bf16x6 split products)"}[args.precision],
         "data": "synthetic (deterministic initial operator Z_c, no dataset)",
         "config": {"workload": f"{L}x{L} TFIM Heisenberg Z_c(t), chi_max={chi}, dt={args.dt}, J=h=1, "
                                f"{FORM_NAMES[args.precision]}, "
