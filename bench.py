@@ -26,11 +26,11 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
 FORM_NAMES = {"fp32": "FP32-MFMA form", "bf16x6": "FP32 form with split-bf16 (x6) GEMMs", "fp64": "FP64 plain form"}
-KERNEL_NAMES = {"gemm": "gemm_pipe_kernel (tiled MFMA GEMM)",
+KERNEL_NAMES = {"gemm": "tile_gemm_kernel<float> / gemm_pipe_kernel (tiled MFMA GEMM)",
                 "gram64": "gram64_kernel (float64-accumulated Gram, MFMA f64)",
                 "mode": "mode_product_kernel (MFMA mode product, factor in LDS)",
                 "leggram": "leg_gram_kernel (MFMA leg Gram of the gauge BP, with its partial sum)",
-                "bsplit": "bsplit_gemm_kernel (six bf16 MFMA products of split float32 operands)"}
+                "bsplit": "tile_gemm_kernel<split> (six bf16 MFMA products of split float32 operands)"}
 
 
 def parse():

@@ -221,12 +221,13 @@ const char* hpt_last_hip_error(void);
  * out4 = {launches, total milliseconds, algorithmic flops (2 M N K per
  * product, half for a symmetric Gram), algorithmic bytes (operands read once,
  * result written once)} for one kernel kind: HPT_PROF_GEMM (gemm_pipe_kernel:
- * general tiled GEMM), HPT_PROF_GRAM64 (gram64_kernel: float64 products
+ * general tiled GEMM, and tile_gemm_kernel<float>: the plain float32
+ * products), HPT_PROF_GRAM64 (gram64_kernel: float64 products
  * and accumulation of float32 data, the CholeskyQR Grams),
  * HPT_PROF_MODE (mode_product_kernel: float32 mode products with the factor
  * resident in LDS), HPT_PROF_LEGGRAM (leg_gram_kernel: float32 leg Grams of
  * the gauge BP, with their partial-sum pass), HPT_PROF_BSPLIT
- * (bsplit_gemm_kernel: the split-bf16 products of HPT_FP32_BF16X6), or -1
+ * (tile_gemm_kernel<split>: the split-bf16 products of HPT_FP32_BF16X6), or -1
  * for all of them.  hpt_profile_gemm_read(out4) is
  * hpt_profile_read(-1, out4).  For the roofline report of the contractions.
  * Returns HPT_EINVAL for a null out4 or an unknown kind. */

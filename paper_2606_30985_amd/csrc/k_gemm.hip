@@ -335,8 +335,9 @@ __global__ __launch_bounds__(256) void gram64_kernel(const float* __restrict__ X
 }
 
 // ---------------------------------------------------------------------------
-// Split-bf16 GEMM C = A B for float32 A (M x K) and B (K x N), column-major,
-// float32 C.  Every operand element x is split to nearest into three bf16
+// Plain products C = A B for float32 A (M x K) and B (K x N), column-major,
+// float32 C, in 128 x 80 tiles, in float32 or in split-bf16 form.
+// Split-bf16: every operand element x is split to nearest into three bf16
 // parts, x = h + m + l (h = bf16(x), m = bf16(x - h), l = x - h - m, which
 // has at most 8 significant bits and is exact in bf16).  The product keeps
 // the six terms down to relative order 2^-16, hh + hm + mh + mm + hl + lh;
@@ -371,13 +372,23 @@ __device__ inline void bsplit_put(const float* v, __bf16* h0, __bf16* m0, __bf16
   *(bf8*)l0 = l;
 }
 
-__global__ __launch_bounds__(256) void bsplit_gemm_kernel(const float* __restrict__ A, int64_t lda,
-                                                          const float* __restrict__ B, int64_t ldb,
-                                                          float* __restrict__ C, int64_t ldc, int M, int N, int K,
-                                                          int ntn, int64_t total, int64_t per_xcd) {
-  constexpr int BM = BS_BM, BN = BS_BN, KC = BS_KC, RS = BS_RS;
-  __shared__ __attribute__((aligned(16))) __bf16 As[3][BM * RS];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[3][BN * RS];
+// SPLIT = false: the same tiling in plain float32 (f32 16x16x4 MFMA, operands
+// as floats in LDS rows of 36: the 16 rows x 4 k-values of an operand read
+// fall on 64 distinct banks), the FP32 form's plain products.
+constexpr int BS_RS32 = 36;
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void tile_gemm_kernel(const float* __restrict__ A, int64_t lda,
+                                                        const float* __restrict__ B, int64_t ldb,
+                                                        float* __restrict__ C, int64_t ldc, int M, int N, int K,
+                                                        int ntn, int64_t total, int64_t per_xcd) {
+  constexpr int BM = BS_BM, BN = BS_BN, KC = BS_KC, RS = BS_RS, RS32 = BS_RS32;
+  constexpr int LDS_BYTES = SPLIT ? 3 * (BM + BN) * RS * 2 : (BM + BN) * RS32 * 4;
+  __shared__ __attribute__((aligned(16))) char smem[LDS_BYTES];
+  __bf16* Ah = (__bf16*)smem;                 // split: planes h, m, l of A, then of B
+  __bf16* Bh = Ah + 3 * BM * RS;
+  float* Af = (float*)smem;                   // float32: A rows, then B columns
+  float* Bf = Af + BM * RS32;
   const int64_t T = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (T >= total) return;
   const int row0 = (int)(T / ntn) * BM, col0 = (int)(T % ntn) * BN;
@@ -409,6 +420,10 @@ __global__ __launch_bounds__(256) void bsplit_gemm_kernel(const float* __restric
       rb[8 + e] = (b1_ok && k1e < K) ? Bp1[k1e] : 0.f;
     }
   };
+  auto put8 = [&](const float* v, float* d) {
+    *(float4*)d = make_float4(v[0], v[1], v[2], v[3]);
+    *(float4*)(d + 4) = make_float4(v[4], v[5], v[6], v[7]);
+  };
   f4 acc[2][5];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -418,45 +433,69 @@ __global__ __launch_bounds__(256) void bsplit_gemm_kernel(const float* __restric
   load(0);
   for (int c = 0; c < nchunks; ++c) {
     __syncthreads();   // every wave is done reading the previous chunk
+    if constexpr (SPLIT) {
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      const int off = ar * RS + 8 * (akg + 2 * g);
-      bsplit_put(ra + 8 * g, &As[0][off], &As[1][off], &As[2][off]);
-    }
-    {
-      const int off = bc0 * RS + 8 * bk0;
-      bsplit_put(rb, &Bs[0][off], &Bs[1][off], &Bs[2][off]);
-    }
-    if (u1_ok) {
-      const int off = bc1 * RS + 8 * bk1;
-      bsplit_put(rb + 8, &Bs[0][off], &Bs[1][off], &Bs[2][off]);
+      for (int g = 0; g < 2; ++g) {
+        const int off = ar * RS + 8 * (akg + 2 * g);
+        bsplit_put(ra + 8 * g, Ah + off, Ah + BM * RS + off, Ah + 2 * BM * RS + off);
+      }
+      {
+        const int off = bc0 * RS + 8 * bk0;
+        bsplit_put(rb, Bh + off, Bh + BN * RS + off, Bh + 2 * BN * RS + off);
+      }
+      if (u1_ok) {
+        const int off = bc1 * RS + 8 * bk1;
+        bsplit_put(rb + 8, Bh + off, Bh + BN * RS + off, Bh + 2 * BN * RS + off);
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < 2; ++g) put8(ra + 8 * g, Af + ar * RS32 + 8 * (akg + 2 * g));
+      put8(rb, Bf + bc0 * RS32 + 8 * bk0);
+      if (u1_ok) put8(rb + 8, Bf + bc1 * RS32 + 8 * bk1);
     }
     __syncthreads();
     if (c + 1 < nchunks) load((c + 1) * KC);
-    bf8 af[2][3];
+    if constexpr (SPLIT) {
+      bf8 af[2][3];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int p = 0; p < 3; ++p) af[i][p] = *(const bf8*)&As[p][(32 * w + 16 * i + (lane & 15)) * RS + 8 * (lane >> 4)];
+        for (int p = 0; p < 3; ++p)
+          af[i][p] = *(const bf8*)(Ah + p * BM * RS + (32 * w + 16 * i + (lane & 15)) * RS + 8 * (lane >> 4));
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      bf8 bf[3];
+      for (int j = 0; j < 5; ++j) {
+        bf8 bf[3];
 #pragma unroll
-      for (int p = 0; p < 3; ++p) bf[p] = *(const bf8*)&Bs[p][(16 * j + (lane & 15)) * RS + 8 * (lane >> 4)];
+        for (int p = 0; p < 3; ++p) bf[p] = *(const bf8*)(Bh + p * BN * RS + (16 * j + (lane & 15)) * RS + 8 * (lane >> 4));
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        // the six products of this k-chunk, smallest terms first, start from
-        // zero and join the running sum in one rounded float32 add: the sum
-        // over K is not carried through the MFMA accumulator (measured: 4x
-        // smaller worst-case error on sums of positive terms)
-        f4 a = {0.f, 0.f, 0.f, 0.f};
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[0], af[i][2], a, 0, 0, 0);
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[2], af[i][0], a, 0, 0, 0);
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[1], af[i][1], a, 0, 0, 0);
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[0], af[i][1], a, 0, 0, 0);
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[1], af[i][0], a, 0, 0, 0);
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[0], af[i][0], a, 0, 0, 0);
-        acc[i][j] += a;
+        for (int i = 0; i < 2; ++i) {
+          // the six products of this k-chunk, smallest terms first, start from
+          // zero and join the running sum in one rounded float32 add: the sum
+          // over K is not carried through the MFMA accumulator (measured: 4x
+          // smaller worst-case error on sums of positive terms)
+          f4 a = {0.f, 0.f, 0.f, 0.f};
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[0], af[i][2], a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[2], af[i][0], a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[1], af[i][1], a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[0], af[i][1], a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[1], af[i][0], a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[0], af[i][0], a, 0, 0, 0);
+          acc[i][j] += a;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KC / 4; ++kk) {
+        const int ko = 4 * kk + (lane >> 4);
+        float af[2], bf[5];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) af[i] = Af[(32 * w + 16 * i + (lane & 15)) * RS32 + ko];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) bf[j] = Bf[(16 * j + (lane & 15)) * RS32 + ko];
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+#pragma unroll
+          for (int i = 0; i < 2; ++i) acc[i][j] = mfma_op(bf[j], af[i], acc[i][j]);
       }
     }
   }
@@ -848,7 +887,7 @@ __global__ __launch_bounds__(1024) void gemm_reduce_kernel(GemmDesc<T> d, int sp
 // stream (process-wide), per kernel kind, for the roofline report.
 constexpr int PROF_CAP = 4096;
 constexpr int PROF_KINDS = 5;   // 0 gemm_pipe_kernel, 1 float64-accumulated Gram (gram64_kernel), 2 mode_product_kernel,
-                                 // 3 leg_gram_kernel, 4 split-bf16 GEMM (bsplit_gemm_kernel)
+                                 // 3 leg_gram_kernel, 4 split-bf16 GEMM (tile_gemm_kernel<true>)
 struct GemmProfile {
   int on = 0;
   int n = 0;
@@ -973,24 +1012,31 @@ int gram64(const GemmDesc<float>& d, double* part, int64_t part_cap, hipStream_t
 }  // namespace
 
 namespace {
-// plain float32 products C = A B (no transposes, batches or scaling) in the
-// split-bf16 form
-bool bsplit_eligible(const GemmDesc<float>& d) {
-  return d.bsplit && !d.acc64 && !d.sym && !d.tA && !d.tB && d.R == 1 && d.Z == 1 && !d.c_double &&
-         d.alpha == 1.0 && d.beta == 0.0;
+// plain float32 products C = A B (no transposes, batches or scaling): the
+// 128 x 80 XCD-ordered tiles, split-bf16 when asked for
+bool tile_eligible(const GemmDesc<float>& d) {
+  return !d.acc64 && !d.sym && !d.tA && !d.tB && d.R == 1 && d.Z == 1 && !d.c_double && d.alpha == 1.0 &&
+         d.beta == 0.0;
 }
 
-int bsplit_gemm(const GemmDesc<float>& d, hipStream_t s) {
+int tile_gemm(const GemmDesc<float>& d, hipStream_t s) {
   const int ntn = (int)ceil_div(d.N, BS_BN);
   const int64_t total = ceil_div(d.M, BS_BM) * (int64_t)ntn;
   const int64_t per_xcd = ceil_div(total, 8);
   if (8 * per_xcd > 0x7fffffff) return -1;
+  const dim3 grid((unsigned)(8 * per_xcd));
   RC_PROF(prof_begin(s));
-  hipLaunchKernelGGL(bsplit_gemm_kernel, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, d.A, d.lda, d.B, d.ldb,
-                     (float*)d.C, d.ldc, d.M, d.N, d.K, ntn, total, per_xcd);
-  HPT_LAUNCH_CHECK("bsplit_gemm_kernel");
+  if (d.bsplit) {
+    hipLaunchKernelGGL(tile_gemm_kernel<true>, grid, dim3(256), 0, s, d.A, d.lda, d.B, d.ldb, (float*)d.C, d.ldc,
+                       d.M, d.N, d.K, ntn, total, per_xcd);
+    HPT_LAUNCH_CHECK("tile_gemm_kernel<split>");
+  } else {
+    hipLaunchKernelGGL(tile_gemm_kernel<false>, grid, dim3(256), 0, s, d.A, d.lda, d.B, d.ldb, (float*)d.C, d.ldc,
+                       d.M, d.N, d.K, ntn, total, per_xcd);
+    HPT_LAUNCH_CHECK("tile_gemm_kernel<float>");
+  }
   const double M = d.M, N = d.N, K = d.K;
-  RC_PROF(prof_end(s, 4, 2.0 * M * N * K, 4.0 * (M * K + K * N + M * N)));
+  RC_PROF(prof_end(s, d.bsplit ? 4 : 0, 2.0 * M * N * K, 4.0 * (M * K + K * N + M * N)));
   return 0;
 }
 }  // namespace
@@ -1006,7 +1052,7 @@ int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s) {
   }();
   if constexpr (std::is_same<T, float>::value) {
     if (gram64_eligible(d, part_cap)) return gram64(d, part, part_cap, s);
-    if (bsplit_eligible(d)) return bsplit_gemm(d, s);
+    if (tile_eligible(d)) return tile_gemm(d, s);
   }
   const bool big = !d.acc64 && forced == 128;
   const int tile = big ? 128 : 64;
