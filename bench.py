@@ -60,7 +60,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(chi, L, dt, sample_chi=60):
+def cpu_baseline(chi, L, dt, sample_chi=70):
     """CPU oracle on one interior-interior bond update (synthetic saturated
     inputs) at sample_chi, extrapolated to the workload's chi by the chi^5
     cost of the update and scaled to layers/s by the layer's bond count."""
