@@ -179,12 +179,12 @@ def main():
     args = parse()
     if args.workload == "batched":
         if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU; run with --gpus 1"}))
+            print(json.dumps({"error": "this library runs on one GPU; run with --gpus 1"}))
             sys.exit(2)
         return batched(args)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only "
-                                   "(DESIGN.md), run with --gpus 1"}))
+        print(json.dumps({"error": "this library runs on one GPU; multi-GPU sharding is a design note only, "
+                                   "run with --gpus 1"}))
         sys.exit(2)
     import torch
     from paper_2606_30985_amd import hpt

@@ -22,8 +22,8 @@ Transverse-Field Ising Model"), written in NumPy/SciPy double precision:
 * ``contract`` -- exact contraction of tiny networks (no BP), for pins.
 * ``run``      -- the time loop producing C(t) trajectories.
 
-Readings of points the paper leaves open are listed in the design doc and stated
-at the function that implements them.  The oracle shares no code with the GPU
+Readings of points the paper leaves open are stated at the function that
+implements them.  The oracle shares no code with the GPU
 path; the only shared module is ``paper_2606_30985_amd.inputs`` (seeded input
 generators, no method arithmetic).
 """

@@ -20,7 +20,7 @@ Paper sections followed (cited by section / equation / algorithm name):
 * Table "Runtime diagnostic measures": gate_err, Bethe norm, sweeps/delta,
   S_e / log chi.
 
-Readings (each listed in the design doc):
+Readings of points the paper leaves open:
 * Bond matrix contracts R_1, R_2 over the cut bond; the SVD acts on the
   (k1*4) x (k2*4) matrix.
 * Gauge BP runs on the norm network sum_p psi psi with chi x chi symmetric

@@ -5,7 +5,7 @@ is a real Pauli coupling maps Pauli strings to real combinations of Pauli
 strings, so in the Pauli basis each gate is a real orthogonal matrix.  The
 step is U(dt) ~ R_z(h dt) R_xx(2 J dt) R_z(h dt) (Eq. trotter).
 
-Reading ("readings"): R_P(theta) = exp(-i theta P / 2), and the
+Reading: R_P(theta) = exp(-i theta P / 2), and the
 signs follow the Hamiltonian of Eq. hamiltonian, H = -J sum XX - h sum Z, so
 that the three factors are the symmetric splitting of exp(-i H dt):
     field half-step   exp(+i (h dt / 2) Z)   on every site
