@@ -4,15 +4,12 @@
 // Propagation", Eq. bethe_raw), the log-space sum with sign tracking
 // (Eq. bethe), and the projections used by the gauge-sign rule.
 #include "misc.h"
+#include "wave.h"
 
 namespace hpt {
 
 namespace {
 
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 __device__ inline double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
