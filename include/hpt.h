@@ -55,7 +55,9 @@ extern "C" {
 #define HPT_FP32_BF16X6 2 /* HPT_FP32_MFMA with the plain float32 products (the reconstruction
                              X (R^-1 M') of every gate) taken as six bf16 MFMA products of the
                              round-to-nearest three-way bf16 split of each operand, accumulated
-                             in float32 (BF16 split precision); everything else as HPT_FP32_MFMA */
+                             in float32 (BF16 split precision); everything else as HPT_FP32_MFMA.
+                             On 10x10 chi_max=100 its C(t) departs from the FP64 form by up to
+                             9e-6 over 30 layers (HPT_FP32_MFMA: 4e-6) */
 
 /* QR strategy (Sec. "Adaptive QR Decomposition") */
 #define HPT_QR_ADAPTIVE    0  /* CholeskyQR2 for tall blocks, Householder otherwise or on failure */
