@@ -99,6 +99,18 @@ def cpu_baseline(chi, L, dt, sample_chi=70):
             "bond_updates_per_s_extrapolated": 1.0 / est}
 
 
+def roofline_peak(kind, precision):
+    """MFMA peak (TFLOP/s of algorithmic flops) for a contraction kind: float64
+    products (the Gram of float32 data, or every product of the float64 form)
+    run on the FP64 MFMA; the split-bf16 products on the bf16 MFMA, six bf16
+    flops per algorithmic flop; the rest on the FP32 MFMA."""
+    if kind == "gram64" or precision == "fp64":
+        return PEAK_TFLOPS["fp64"]
+    if kind == "bsplit":
+        return PEAK_TFLOPS["bf16"] / 6.0
+    return PEAK_TFLOPS["fp32"]
+
+
 def traffic_ratio(kernel_key):
     """HBM bytes per algorithmic byte of a kernel family, from the committed
     PMC summary; None when the kernel source has changed since it was taken."""
@@ -239,15 +251,7 @@ def main():
     value = args.steps / elapsed
     ratio = traffic_ratio(dom)
     achieved = prof["flops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else 0.0
-    # float64 products (the Gram of float32 data, or every product of the
-    # float64 form) run on the FP64 MFMA; the split-bf16 products on the bf16
-    # MFMA, each of their algorithmic flops costing six bf16 flops
-    if dom == "gram64" or args.precision == "fp64":
-        peak = PEAK_TFLOPS["fp64"]
-    elif dom == "bsplit":
-        peak = PEAK_TFLOPS["bf16"] / 6.0
-    else:
-        peak = PEAK_TFLOPS["fp32"]
+    peak = roofline_peak(dom, args.precision)
     out = {
         "metric": "Trotter layers/sec at 10x10 chi=100 (|dC(t)| vs FP64 oracle); bond updates/sec",
         "value": value,

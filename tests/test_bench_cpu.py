@@ -34,3 +34,14 @@ def test_traffic_ratio_follows_the_kernel_source(tmp_path, monkeypatch):
     (tmp_path / "paper_2606_30985_amd" / "csrc" / "k_gemm.hip").write_text(src + "\n// changed\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.traffic_ratio("mode") is None
+
+
+def test_roofline_peak_per_kind():
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.roofline_peak("mode", "fp32") == 157.3
+    assert bench.roofline_peak("gemm", "bf16x6") == 157.3
+    assert bench.roofline_peak("gram64", "fp32") == 78.6
+    assert bench.roofline_peak("mode", "fp64") == 78.6
+    assert abs(bench.roofline_peak("bsplit", "bf16x6") - 2500.0 / 6) < 1e-9
+
