@@ -117,8 +117,8 @@ _MIX1 = np.uint64(0xBF58476D1CE4E5B9)
 _MIX2 = np.uint64(0x94D049BB133111EB)
 
 
-def gauge_sign_weights(n):
-    """w_i = u_i - 1/2 with u_i the 53-bit uniform of SplitMix64 output i.
+def splitmix64(n):
+    """The first n outputs of SplitMix64 started from state 0, as uint64.
 
     SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number
     generators", OOPSLA 2014): state_i = (i + 1) * gamma, then the finaliser
@@ -129,6 +129,12 @@ def gauge_sign_weights(n):
         z = (z ^ (z >> np.uint64(30))) * _MIX1
         z = (z ^ (z >> np.uint64(27))) * _MIX2
         z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def gauge_sign_weights(n):
+    """w_i = u_i - 1/2 with u_i = (top 53 bits of SplitMix64 output i) * 2^-53."""
+    z = splitmix64(n)
     return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53) - 0.5
 
 

@@ -19,10 +19,14 @@ CASES = {
     # 4x4, centre (1,1), dt 0.05, 40 steps, chi_max 20, FP64, uniform-init BP, damping 0.5, tol 1e-10
     "oracle_4x4_chi20": (dict(Lx=4, Ly=4, J=1.0, h=1.0, dt=0.05, chi_max=20, bp_alpha=0.5, bp_tol=1e-10), 40),
     "oracle_4x4_chi40": (dict(Lx=4, Ly=4, J=1.0, h=1.0, dt=0.05, chi_max=40, bp_alpha=0.5, bp_tol=1e-10), 40),
+    "oracle_4x4_chi60": (dict(Lx=4, Ly=4, J=1.0, h=1.0, dt=0.05, chi_max=60, bp_alpha=0.5, bp_tol=1e-10), 40),
     "oracle_3x3_chi8": (dict(Lx=3, Ly=3, J=1.0, h=1.0, dt=0.05, chi_max=8, bp_alpha=0.5, bp_tol=1e-10), 20),
     # 10x10 (the benchmark lattice) at chi_max 30, FP64 cutoff, the benchmark's BP settings, 12 layers
     "oracle_10x10_chi30": (dict(Lx=10, Ly=10, J=1.0, h=1.0, dt=0.05, chi_max=30, bp_alpha=0.5, bp_tol=1e-5,
                                 bp_max_sweeps=100, bp_init="warm", meas_tol=1e-10, meas_max_sweeps=400), 12),
+    # 11x11 (odd, centre (5,5): C4-symmetric placement) at chi_max 30, same settings, 10 layers
+    "oracle_11x11_chi30": (dict(Lx=11, Ly=11, J=1.0, h=1.0, dt=0.05, chi_max=30, bp_alpha=0.5, bp_tol=1e-5,
+                                bp_max_sweeps=100, bp_init="warm", meas_tol=1e-10, meas_max_sweeps=400), 10),
     # the 4x4 chi_max 20 run with the trap remediation (the layer-40 trap is retried)
     "oracle_4x4_chi20_trap_retry": (dict(Lx=4, Ly=4, J=1.0, h=1.0, dt=0.05, chi_max=20, bp_alpha=0.5, bp_tol=1e-10,
                                          trap_retry=True), 40),
