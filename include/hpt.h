@@ -212,6 +212,39 @@ int hpt_get_meas_messages(hpt_sim* sim, int32_t bond, int32_t dir, double* host,
  * (the other runs stop at their next layer).  Blocks until all runs are done. */
 int hpt_run_batch(hpt_sim* const* sims, int32_t n, const int32_t* nsteps, hpt_measurement* const* out);
 
+/* Checkpoint and resume (long runs; the benchmark's fixed saturated state).
+ * The image holds the whole simulation state: live site tensors in the storage
+ * type of the handle's precision, gauge and measurement messages, bond
+ * dimensions, Vidal values, the layer counter and the diagnostics that the
+ * next hpt_measure reads (trap rule).  A handle resumed from an image
+ * continues bit-identically to the handle that wrote it (every kernel has a
+ * fixed reduction order).
+ * where: HPT_MEM_HOST (buf is host memory) or HPT_MEM_DEVICE (buf is device
+ * memory on the handle's GPU).  buf is caller-owned.
+ * hpt_checkpoint_bytes: size of the image of the current state.
+ * hpt_checkpoint_save: writes the image; HPT_ENOMEM when cap is smaller than
+ *   hpt_checkpoint_bytes (nothing written).  Synchronises the stream.
+ * hpt_checkpoint_load: HPT_EINVAL when the image is not one of this library or
+ *   was written by a handle with another lattice, chi_max, precision, J, h or
+ *   dt, or when bytes is shorter than the image; the handle is unchanged then.
+ *   Synchronises the stream. */
+#define HPT_MEM_HOST   0
+#define HPT_MEM_DEVICE 1
+int hpt_checkpoint_bytes(hpt_sim* sim, uint64_t* bytes);
+int hpt_checkpoint_save(hpt_sim* sim, void* buf, uint64_t cap, int32_t where);
+int hpt_checkpoint_load(hpt_sim* sim, const void* buf, uint64_t bytes, int32_t where);
+
+/* Per-phase timing of one handle with HIP events on its stream (the benchmark's
+ * split of a layer): enable = 1 creates the events and clears the totals,
+ * 0 removes them.  While enabled, every layer adds the milliseconds of its
+ * gate phase (both field half-steps and the four colours, rows a1-a7) and of
+ * its gauge BP (row a8), and every hpt_measure those of the measurement BP
+ * and Bethe sum (row a9); each phase boundary waits for its event.
+ * hpt_phase_read fills out7 = {gate ms, gauge-BP ms, measurement ms, layers,
+ * gauge sweeps, measurements, measurement sweeps}. */
+int hpt_phase_timing(hpt_sim* sim, int32_t enable);
+int hpt_phase_read(hpt_sim* sim, double* out7);
+
 int hpt_destroy(hpt_sim* sim);
 
 const char* hpt_strerror(int code);
@@ -241,6 +274,26 @@ const char* hpt_last_hip_error(void);
 int hpt_profile_gemm(int32_t enable);
 int hpt_profile_gemm_read(double* out4);
 int hpt_profile_read(int32_t kind, double* out4);
+
+/* Float64 Gram of float32 data, the first CholeskyQR pass of the gate update
+ * (Sec. "Adaptive QR Decomposition", Eq. cholqr: G = X^T X of the absorbed,
+ * permuted site matrix, here with float64 products and sums as the paper
+ * recommends for the Gram).
+ * X: device, float32, m x n column-major with leading dimension ldx >= m.
+ * G: device, float64, n x n column-major with leading dimension ldg >= n;
+ *    both triangles are written.
+ * workspace: device scratch of at least hpt_gram64_workspace_bytes(m, n)
+ *    bytes (per-split partial tiles, at most HPT_GRAM64_PART_MAX; its contents
+ *    need no clearing and are overwritten), caller-owned.
+ * The rows of X are reduced in a fixed order: the same inputs give the same G
+ * bit for bit.  Stream-ordered on hip_stream, asynchronous.  n == 0 does
+ * nothing.  Returns HPT_EINVAL for negative sizes, m >= 2^31 - 64, ldx < m,
+ * ldg < n or null pointers (X may be null when m == 0: G = 0); HPT_ENOMEM for a short workspace (before any
+ * launch); HPT_EHIP when a launch fails. */
+#define HPT_GRAM64_PART_MAX (64ull << 20)
+int hpt_gram64_workspace_bytes(int64_t m, int32_t n, uint64_t* bytes);
+int hpt_gram64(const float* X, int64_t m, int32_t n, int64_t ldx, double* G, int64_t ldg, void* workspace,
+               uint64_t workspace_bytes, void* hip_stream);
 
 /* Permute a column-major tensor on the device (Sec. "GPU Tensor Permutation").
  * in/out: device pointers, not overlapping; ndim <= 8; dims of the input;

@@ -56,6 +56,12 @@ struct GemmDesc {
 template <typename T>
 int gemm(const GemmDesc<T>& d, double* part, int64_t part_cap, hipStream_t s);
 
+// float64 Gram of float32 data (CholeskyQR first pass): row splits for a
+// partial buffer of part_cap doubles, and the launch (part: splits n^2 doubles)
+int gram64_splits(int64_t m, int n, int64_t part_cap);
+int gram64_launch(const float* X, int64_t ldx, int m, int n, double* G, int64_t ldg, int splits, double* part,
+                  hipStream_t s);
+
 // process-wide event timing of the contraction launches; kind 0 gemm_pipe_kernel,
 // 1 the float64-accumulated Gram of float data, 2 mode_product_kernel, 3 leg_gram_kernel, -1 all
 int gemm_profile(int enable);

@@ -132,4 +132,9 @@ struct hpt_sim {
   // last measurement (step, C, gate error) and the one of the layer before
   int rec_step, prv_step;
   double rec_C, rec_gate_err, prv_C, prv_gate_err;
+  // per-phase timing (hpt_phase_timing): HIP events on the handle's stream
+  bool phase_on;
+  hipEvent_t phase_ev[5];
+  double phase_ms[3];           // gate phase (rows a1-a7), gauge BP (a8), measurement (a9)
+  int64_t phase_count[4];       // layers, gauge sweeps, measurements, measurement sweeps
 };

@@ -256,6 +256,15 @@ int sync_stream(hpt_sim* s) {
   return 0;
 }
 
+// elapsed milliseconds between two recorded events (waits for the second)
+int event_ms(hipEvent_t a, hipEvent_t b, double* ms) {
+  HPT_HIP(hipEventSynchronize(b));
+  float f = 0.0f;
+  HPT_HIP(hipEventElapsedTime(&f, a, b));
+  *ms = f;
+  return 0;
+}
+
 template <typename J>
 int stage(hpt_sim* s, const J* host, int n, J** dev) {
   const uint64_t bytes = align_up(sizeof(J) * (uint64_t)std::max(n, 1));
@@ -1361,6 +1370,7 @@ int measure_t(hpt_sim* s, hpt_measurement* out) {
     s->prv_C = s->rec_C;
     s->prv_gate_err = s->rec_gate_err;
   }
+  if (s->phase_on) HPT_HIP(hipEventRecord(s->phase_ev[3], s->stream));
   MeasResult mr;
   RC(meas_bp_t<T>(s, alpha, mr));
   uint32_t flags = s->layer_flags | mr.flags;
@@ -1379,8 +1389,19 @@ int measure_t(hpt_sim* s, hpt_measurement* out) {
       mr = r2;
       flags = (flags & ~HPT_FLAG_BETHE_ZERO) | r2.flags | HPT_FLAG_TRAP_REMEDIATED;
     } else {
+      // the first value stands: rerun its BP (deterministic) so that the
+      // measurement messages left in the handle are the ones of the reported C
+      RC(meas_bp_t<T>(s, alpha, mr));
       flags |= HPT_FLAG_TRAP_UNRESOLVED;
     }
+  }
+  if (s->phase_on) {
+    HPT_HIP(hipEventRecord(s->phase_ev[4], s->stream));
+    double m = 0.0;
+    RC(event_ms(s->phase_ev[3], s->phase_ev[4], &m));
+    s->phase_ms[2] += m;
+    s->phase_count[2] += 1;
+    s->phase_count[3] += mr.sweeps;
   }
   const double C = mr.C, logC = mr.logC, delta = mr.delta;
   const int sign = mr.sign, sweeps = mr.sweeps;
@@ -1413,15 +1434,27 @@ template <typename T>
 int layer_t(hpt_sim* s) {
   s->layer_gate_err = 0.0;
   s->layer_flags = 0;
+  if (s->phase_on) HPT_HIP(hipEventRecord(s->phase_ev[0], s->stream));
   RC(apply_field_t<T>(s));
   for (int c = 0; c < 4; ++c) RC(gate_colour<T>(s, s->colour_bonds[c]));
   RC(apply_field_t<T>(s));
+  if (s->phase_on) HPT_HIP(hipEventRecord(s->phase_ev[1], s->stream));
   s->gauge_sweeps = 0;
   s->gauge_delta = 0.0;
   if (s->cfg.gauge_bp) {
     RC(gauge_bp_t<T>(s, s->cfg.bp_init, nullptr, nullptr));
     if (s->gauge_delta >= s->cfg.bp_tol) s->layer_flags |= HPT_FLAG_BP_NOT_CONVERGED_GAUGE;
     if (s->gauge_sweeps >= s->cfg.trap_sweeps && s->gauge_delta < s->cfg.bp_tol) s->layer_flags |= HPT_FLAG_TRAP_CANDIDATE;
+  }
+  if (s->phase_on) {
+    HPT_HIP(hipEventRecord(s->phase_ev[2], s->stream));
+    double g = 0.0, b = 0.0;
+    RC(event_ms(s->phase_ev[0], s->phase_ev[1], &g));
+    RC(event_ms(s->phase_ev[1], s->phase_ev[2], &b));
+    s->phase_ms[0] += g;
+    s->phase_ms[1] += b;
+    s->phase_count[0] += 1;
+    s->phase_count[1] += s->gauge_sweeps;
   }
   double sf = 0.0;
   if (s->chi_max > 1)
@@ -1691,6 +1724,7 @@ int hpt_run_batch(hpt_sim* const* sims, int32_t n, const int32_t* nsteps, hpt_me
       if (i >= n || err.load() != 0) return;
       hpt_sim* s = sims[i];
       for (int k = 0; k < nsteps[i]; ++k) {
+        if (err.load() != 0) return;   // another run failed: stop at this layer boundary
         int r = s->fp32 ? layer_t<float>(s) : layer_t<double>(s);
         if (!r && out && out[i]) r = s->fp32 ? measure_t<float>(s, out[i] + k) : measure_t<double>(s, out[i] + k);
         if (r) {
@@ -1835,9 +1869,209 @@ int hpt_get_meas_messages(hpt_sim* s, int32_t bond, int32_t dir, double* host, i
   return HPT_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// checkpoint image: header, bond dimensions, Vidal values, gauge messages,
+// measurement messages, live site tensors; every section 256-byte aligned
+
+namespace {
+
+struct CkptHeader {
+  char magic[8];
+  int32_t version, Lx, Ly, chi_max, precision, N, nb, step;
+  int32_t gauge_sweeps, rec_step, prv_step;
+  uint32_t layer_flags;
+  double J, h, dt;
+  double layer_gate_err, layer_sfrac, gauge_delta, bethe_norm, rec_C, rec_gate_err, prv_C, prv_gate_err;
+  uint64_t off_chi, off_lam, off_gmsg, off_mmsg, off_psi, total;
+};
+const char CKPT_MAGIC[8] = {'H', 'P', 'T', 'C', 'K', 'P', 'T', '1'};
+
+// section offsets of an image for the bond dimensions chi
+void ckpt_layout(const hpt_sim* s, const std::vector<int>& chi, CkptHeader& h) {
+  uint64_t o = align_up(sizeof(CkptHeader));
+  h.off_chi = o;
+  o = align_up(o + 4ull * s->nb);
+  h.off_lam = o;
+  for (int c : chi) o += 8ull * c;
+  o = align_up(o);
+  h.off_gmsg = o;
+  for (int c : chi) o += 2ull * 8 * c * c;
+  o = align_up(o);
+  h.off_mmsg = o;
+  for (int c : chi) o += 2ull * 8 * c;
+  o = align_up(o);
+  h.off_psi = o;
+  for (int v = 0; v < s->N; ++v) {
+    uint64_t n = 4;
+    for (int l = 0; l < s->sites[v].deg; ++l) n *= chi[s->sites[v].bond[l]];
+    o = align_up(o + n * s->elem);
+  }
+  h.total = o;
+}
+
+// one copy between the image and the handle's device memory
+int ckpt_copy(hpt_sim* s, char* img, uint64_t off, void* dev, uint64_t bytes, int where, bool save) {
+  if (bytes == 0) return 0;
+  if (where == HPT_MEM_DEVICE) {
+    if (save)
+      HPT_HIP(hipMemcpyAsync(img + off, dev, bytes, hipMemcpyDeviceToDevice, s->stream));
+    else
+      HPT_HIP(hipMemcpyAsync(dev, img + off, bytes, hipMemcpyDeviceToDevice, s->stream));
+  } else {
+    if (save)
+      HPT_HIP(hipMemcpy(img + off, dev, bytes, hipMemcpyDeviceToHost));
+    else
+      HPT_HIP(hipMemcpy(dev, img + off, bytes, hipMemcpyHostToDevice));
+  }
+  return 0;
+}
+
+// the device sections (messages and site tensors) in image order
+int ckpt_device_sections(hpt_sim* s, const CkptHeader& h, char* img, int where, bool save) {
+  uint64_t o = h.off_gmsg;
+  for (int b = 0; b < s->nb; ++b)
+    for (int d = 0; d < 2; ++d) {
+      const uint64_t n = 8ull * s->chi[b] * s->chi[b];
+      RC(ckpt_copy(s, img, o, gmsg_slot(s, b, d), n, where, save));
+      o += n;
+    }
+  o = h.off_mmsg;
+  for (int b = 0; b < s->nb; ++b)
+    for (int d = 0; d < 2; ++d) {
+      const uint64_t n = 8ull * s->chi[b];
+      RC(ckpt_copy(s, img, o, mmsg_slot(s, b, d), n, where, save));
+      o += n;
+    }
+  o = h.off_psi;
+  for (int v = 0; v < s->N; ++v) {
+    uint64_t n = 4;
+    for (int l = 0; l < s->sites[v].deg; ++l) n *= s->chi[s->sites[v].bond[l]];
+    RC(ckpt_copy(s, img, o, s->sites[v].psi, n * s->elem, where, save));
+    o = align_up(o + n * s->elem);
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hpt_checkpoint_bytes(hpt_sim* s, uint64_t* bytes) {
+  if (!s || !bytes) return HPT_EINVAL;
+  CkptHeader h;
+  ckpt_layout(s, s->chi, h);
+  *bytes = h.total;
+  return HPT_OK;
+}
+
+int hpt_checkpoint_save(hpt_sim* s, void* buf, uint64_t cap, int32_t where) {
+  if (!s || !buf || (where != HPT_MEM_HOST && where != HPT_MEM_DEVICE)) return HPT_EINVAL;
+  CkptHeader h;
+  std::memset(&h, 0, sizeof(h));
+  ckpt_layout(s, s->chi, h);
+  if (cap < h.total) return HPT_ENOMEM;
+  std::memcpy(h.magic, CKPT_MAGIC, 8);
+  h.version = 1;
+  h.Lx = s->cfg.Lx; h.Ly = s->cfg.Ly; h.chi_max = s->chi_max; h.precision = s->cfg.precision;
+  h.N = s->N; h.nb = s->nb; h.step = s->step;
+  h.gauge_sweeps = s->gauge_sweeps; h.rec_step = s->rec_step; h.prv_step = s->prv_step;
+  h.layer_flags = s->layer_flags;
+  h.J = s->cfg.J; h.h = s->cfg.h; h.dt = s->cfg.dt;
+  h.layer_gate_err = s->layer_gate_err; h.layer_sfrac = s->layer_sfrac; h.gauge_delta = s->gauge_delta;
+  h.bethe_norm = s->bethe_norm; h.rec_C = s->rec_C; h.rec_gate_err = s->rec_gate_err;
+  h.prv_C = s->prv_C; h.prv_gate_err = s->prv_gate_err;
+  // host part: header, chi, lambda
+  std::vector<char> blob(h.off_gmsg, 0);
+  std::memcpy(blob.data(), &h, sizeof(h));
+  for (int b = 0; b < s->nb; ++b) std::memcpy(blob.data() + h.off_chi + 4ull * b, &s->chi[b], 4);
+  uint64_t o = h.off_lam;
+  for (int b = 0; b < s->nb; ++b) {
+    std::memcpy(blob.data() + o, s->lam[b].data(), 8ull * s->chi[b]);
+    o += 8ull * s->chi[b];
+  }
+  RC(sync_stream(s));
+  char* img = (char*)buf;
+  if (where == HPT_MEM_DEVICE)
+    HPT_HIP(hipMemcpy(img, blob.data(), blob.size(), hipMemcpyHostToDevice));
+  else
+    std::memcpy(img, blob.data(), blob.size());
+  RC(ckpt_device_sections(s, h, img, where, true));
+  return sync_stream(s);
+}
+
+int hpt_checkpoint_load(hpt_sim* s, const void* buf, uint64_t bytes, int32_t where) {
+  if (!s || !buf || (where != HPT_MEM_HOST && where != HPT_MEM_DEVICE)) return HPT_EINVAL;
+  if (bytes < sizeof(CkptHeader)) return HPT_EINVAL;
+  char* img = (char*)buf;
+  RC(sync_stream(s));
+  CkptHeader h;
+  if (where == HPT_MEM_DEVICE)
+    HPT_HIP(hipMemcpy(&h, img, sizeof(h), hipMemcpyDeviceToHost));
+  else
+    std::memcpy(&h, img, sizeof(h));
+  if (std::memcmp(h.magic, CKPT_MAGIC, 8) != 0 || h.version != 1 || h.Lx != s->cfg.Lx || h.Ly != s->cfg.Ly ||
+      h.chi_max != s->chi_max || h.precision != s->cfg.precision || h.N != s->N || h.nb != s->nb ||
+      h.J != s->cfg.J || h.h != s->cfg.h || h.dt != s->cfg.dt || h.total > bytes || h.off_gmsg > h.total)
+    return HPT_EINVAL;
+  std::vector<char> blob(h.off_gmsg);
+  if (where == HPT_MEM_DEVICE)
+    HPT_HIP(hipMemcpy(blob.data(), img, blob.size(), hipMemcpyDeviceToHost));
+  else
+    std::memcpy(blob.data(), img, blob.size());
+  std::vector<int> chi(s->nb);
+  for (int b = 0; b < s->nb; ++b) {
+    std::memcpy(&chi[b], blob.data() + h.off_chi + 4ull * b, 4);
+    if (chi[b] < 1 || chi[b] > s->chi_max) return HPT_EINVAL;
+  }
+  CkptHeader chk;
+  ckpt_layout(s, chi, chk);
+  if (chk.total != h.total || chk.off_gmsg != h.off_gmsg || chk.off_psi != h.off_psi) return HPT_EINVAL;
+  s->chi = chi;
+  uint64_t o = h.off_lam;
+  for (int b = 0; b < s->nb; ++b) {
+    s->lam[b].resize(chi[b]);
+    std::memcpy(s->lam[b].data(), blob.data() + o, 8ull * chi[b]);
+    o += 8ull * chi[b];
+  }
+  s->step = h.step;
+  s->gauge_sweeps = h.gauge_sweeps; s->rec_step = h.rec_step; s->prv_step = h.prv_step;
+  s->layer_flags = h.layer_flags;
+  s->layer_gate_err = h.layer_gate_err; s->layer_sfrac = h.layer_sfrac; s->gauge_delta = h.gauge_delta;
+  s->bethe_norm = h.bethe_norm; s->rec_C = h.rec_C; s->rec_gate_err = h.rec_gate_err;
+  s->prv_C = h.prv_C; s->prv_gate_err = h.prv_gate_err;
+  RC(ckpt_device_sections(s, h, img, where, false));
+  return sync_stream(s);
+}
+
+int hpt_phase_timing(hpt_sim* s, int32_t enable) {
+  if (!s) return HPT_EINVAL;
+  RC(sync_stream(s));
+  if (enable && !s->phase_on) {
+    for (hipEvent_t& e : s->phase_ev) HPT_HIP(hipEventCreate(&e));
+    s->phase_on = true;
+  } else if (!enable && s->phase_on) {
+    for (hipEvent_t e : s->phase_ev) (void)hipEventDestroy(e);
+    s->phase_on = false;
+  }
+  for (double& m : s->phase_ms) m = 0.0;
+  for (int64_t& c : s->phase_count) c = 0;
+  return HPT_OK;
+}
+
+int hpt_phase_read(hpt_sim* s, double* out7) {
+  if (!s || !out7) return HPT_EINVAL;
+  for (int i = 0; i < 3; ++i) out7[i] = s->phase_ms[i];
+  for (int i = 0; i < 4; ++i) out7[3 + i] = (double)s->phase_count[i];
+  return HPT_OK;
+}
+
 int hpt_destroy(hpt_sim* s) {
   if (!s) return HPT_EINVAL;
   (void)hipStreamSynchronize(s->stream);
+  if (s->phase_on)
+    for (hipEvent_t e : s->phase_ev) (void)hipEventDestroy(e);
   if (s->jobs_host) (void)hipHostFree(s->jobs_host);
   if (s->hscratch) (void)hipHostFree(s->hscratch);
   if (s->own_arena && s->arena) (void)hipFree(s->arena);

@@ -969,6 +969,53 @@ int gemm_profile_read(int kind, double* out4) {
   return 0;
 }
 
+// Row splits of the float64 Gram of an m x n X: doubled while the grid stays
+// within ~4096 workgroups, every split keeps at least 16 chunks of rows and
+// the partial tiles (splits x n x n doubles) fit part_cap.
+int gram64_splits(int64_t m, int n, int64_t part_cap) {
+  const int64_t tiles_m = ceil_div(n, 64);
+  const int64_t tiles = tiles_m * (tiles_m + 1) / 2;
+  const int64_t chunks = ceil_div(m, G64_TK);
+  int splits = 1;
+  while (splits < 128 && tiles * splits * 2 <= 4096 && chunks / (splits * 2) >= 16 &&
+         (int64_t)splits * 2 * n * n <= part_cap)
+    splits *= 2;
+  return splits;
+}
+
+// G (n x n, leading dimension ldg, both triangles) = X^T X in float64 for a
+// float32 X (m x n, column-major, leading dimension ldx): gram64_kernel writes
+// every split's upper 16-blocks (all of them, zeros for an empty split) into
+// part (splits x n x n doubles), gemm_reduce_kernel sums the splits in a fixed
+// order and mirrors.  Nothing in part has to be cleared before the call.
+int gram64_launch(const float* X, int64_t ldx, int m, int n, double* G, int64_t ldg, int splits, double* part,
+                  hipStream_t s) {
+  if (n <= 0) return 0;
+  const int tiles_m = (int)ceil_div(n, 64);
+  const int64_t tiles = (int64_t)tiles_m * (tiles_m + 1) / 2;
+  const int chunks = (int)ceil_div(m, G64_TK);
+  const bool vec = ldx % 4 == 0 && ((uintptr_t)X & 15) == 0;
+  const unsigned grid = (unsigned)(tiles * splits);
+  if (vec)
+    hipLaunchKernelGGL(gram64_kernel<true>, dim3(grid), dim3(256), 0, s, X, ldx, m, n, (int)tiles, splits, chunks,
+                       part);
+  else
+    hipLaunchKernelGGL(gram64_kernel<false>, dim3(grid), dim3(256), 0, s, X, ldx, m, n, (int)tiles, splits, chunks,
+                       part);
+  HPT_LAUNCH_CHECK("gram64_kernel");
+  GemmDesc<float> d{};
+  d.M = n; d.N = n; d.K = m; d.R = 1; d.Z = 1;
+  d.A = X; d.lda = ldx; d.tA = 1;
+  d.B = X; d.ldb = ldx; d.tB = 0;
+  d.C = G; d.ldc = ldg; d.c_double = 1;
+  d.alpha = 1.0; d.beta = 0.0; d.sym = 1; d.acc64 = 1;
+  const int64_t blocks = ceil_div((int64_t)n * n, 64);
+  hipLaunchKernelGGL(gemm_reduce_kernel<float>, dim3((unsigned)blocks), dim3(1024), 0, s, d, splits,
+                     (const double*)part);
+  HPT_LAUNCH_CHECK("gemm_reduce_kernel");
+  return 0;
+}
+
 namespace {
 // the float64-accumulated Gram G = X^T X of a float32 X, written whole
 // (mirrored) into a float64 C, is served by gram64_kernel
@@ -979,34 +1026,14 @@ bool gram64_eligible(const GemmDesc<float>& d, int64_t part_cap) {
 
 int gram64(const GemmDesc<float>& d, double* part, int64_t part_cap, hipStream_t s) {
   const int n = d.M, m = d.K;
-  const int tiles_m = (int)ceil_div(n, 64);
-  const int64_t tiles = (int64_t)tiles_m * (tiles_m + 1) / 2;
-  const int chunks = (int)ceil_div(m, G64_TK);
-  // split the rows of X while the grid stays within ~4096 workgroups, each
-  // split keeps at least 16 chunks, and the partials fit the scratch
-  int splits = 1;
-  while (splits < 128 && tiles * splits * 2 <= 4096 && chunks / (splits * 2) >= 16 &&
-         (int64_t)splits * 2 * n * n <= part_cap)
-    splits *= 2;
-  const bool vec = d.lda % 4 == 0 && ((uintptr_t)d.A & 15) == 0;
+  const int splits = gram64_splits(m, n, part_cap);
   RC_PROF(prof_begin(s));
-  const unsigned grid = (unsigned)(tiles * splits);
-  if (vec)
-    hipLaunchKernelGGL(gram64_kernel<true>, dim3(grid), dim3(256), 0, s, d.A, d.lda, m, n, (int)tiles, splits, chunks,
-                       part);
-  else
-    hipLaunchKernelGGL(gram64_kernel<false>, dim3(grid), dim3(256), 0, s, d.A, d.lda, m, n, (int)tiles, splits,
-                       chunks, part);
-  HPT_LAUNCH_CHECK("gram64_kernel");
+  RC_PROF(gram64_launch(d.A, d.lda, m, n, (double*)d.C, d.ldc, splits, part, s));
   {
     const double N = n, K = m;
     // algorithmic: half the products of a full n x n product; X read once, G written once
     RC_PROF(prof_end(s, 1, N * N * K, 4.0 * K * N + 8.0 * N * N));
   }
-  const int64_t blocks = ceil_div((int64_t)n * n, 64);
-  hipLaunchKernelGGL(gemm_reduce_kernel<float>, dim3((unsigned)blocks), dim3(1024), 0, s, d, splits,
-                     (const double*)part);
-  HPT_LAUNCH_CHECK("gemm_reduce_kernel");
   return 0;
 }
 }  // namespace

@@ -1,0 +1,48 @@
+// Stand-alone C ABI entry points of single steps of the gate update, on
+// caller device buffers (no simulator handle): the float64 Gram of the
+// CholeskyQR first pass (Sec. "Adaptive QR Decomposition", Eq. cholqr).
+#include <cstdint>
+
+#include "../../include/hpt.h"
+#include "common.h"
+
+namespace hpt {
+namespace {
+
+// shared argument checks; *splits receives the row-split count
+int gram64_args(const float* X, int64_t m, int32_t n, int64_t ldx, const double* G, int64_t ldg, int* splits) {
+  if (m < 0 || n < 0 || m > 0x7fffffff - 64) return HPT_EINVAL;
+  if (n == 0) {
+    *splits = 0;
+    return HPT_OK;
+  }
+  if ((!X && m > 0) || !G || ldx < m || ldg < n) return HPT_EINVAL;
+  *splits = gram64_splits(m, n, (int64_t)(HPT_GRAM64_PART_MAX / 8));
+  return HPT_OK;
+}
+
+}  // namespace
+}  // namespace hpt
+
+using namespace hpt;
+
+extern "C" {
+
+int hpt_gram64_workspace_bytes(int64_t m, int32_t n, uint64_t* bytes) {
+  if (!bytes || m < 0 || n < 0 || m > 0x7fffffff - 64) return HPT_EINVAL;
+  *bytes = n == 0 ? 0 : (uint64_t)gram64_splits(m, n, (int64_t)(HPT_GRAM64_PART_MAX / 8)) * n * n * 8;
+  return HPT_OK;
+}
+
+int hpt_gram64(const float* X, int64_t m, int32_t n, int64_t ldx, double* G, int64_t ldg, void* workspace,
+               uint64_t workspace_bytes, void* hip_stream) {
+  int splits = 0;
+  const int r = gram64_args(X, m, n, ldx, G, ldg, &splits);
+  if (r || n == 0) return r;
+  const uint64_t need = (uint64_t)splits * n * n * 8;
+  if (!workspace || workspace_bytes < need) return HPT_ENOMEM;
+  if (gram64_launch(X, ldx, (int)m, n, G, ldg, splits, (double*)workspace, (hipStream_t)hip_stream)) return HPT_EHIP;
+  return HPT_OK;
+}
+
+}  // extern "C"

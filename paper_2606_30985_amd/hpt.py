@@ -102,6 +102,13 @@ def _load():
         "hpt_profile_gemm_read": [ctypes.POINTER(dbl)],
         "hpt_profile_read": [i32, ctypes.POINTER(dbl)],
         "hpt_run_batch": [ctypes.POINTER(ctypes.c_void_p), i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_void_p)],
+        "hpt_checkpoint_bytes": [P, ctypes.POINTER(u64)],
+        "hpt_checkpoint_save": [P, P, u64, i32],
+        "hpt_checkpoint_load": [P, P, u64, i32],
+        "hpt_phase_timing": [P, i32],
+        "hpt_phase_read": [P, ctypes.POINTER(dbl)],
+        "hpt_gram64_workspace_bytes": [ctypes.c_int64, i32, ctypes.POINTER(u64)],
+        "hpt_gram64": [P, ctypes.c_int64, i32, ctypes.c_int64, P, ctypes.c_int64, P, u64, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -121,7 +128,12 @@ EXPORTED = ["hpt_config_default", "hpt_required_bytes", "hpt_state_bytes", "hpt_
             "hpt_measure", "hpt_get_chi", "hpt_get_bond_spectrum", "hpt_get_site_tensor",
             "hpt_set_site_tensor", "hpt_get_messages", "hpt_set_messages",
             "hpt_get_meas_messages", "hpt_destroy", "hpt_strerror", "hpt_last_hip_error",
-            "hpt_permute", "hpt_profile_gemm", "hpt_profile_gemm_read", "hpt_profile_read", "hpt_run_batch"]
+            "hpt_permute", "hpt_profile_gemm", "hpt_profile_gemm_read", "hpt_profile_read", "hpt_run_batch",
+            "hpt_checkpoint_bytes", "hpt_checkpoint_save", "hpt_checkpoint_load", "hpt_phase_timing",
+            "hpt_phase_read", "hpt_gram64_workspace_bytes", "hpt_gram64"]
+
+HPT_MEM_HOST = 0
+HPT_MEM_DEVICE = 1
 
 
 def profile_gemm(enable=True):
@@ -311,10 +323,70 @@ class Simulator:
                                         c), "hpt_get_meas_messages")
         return out
 
+    def checkpoint_bytes(self):
+        n = ctypes.c_uint64()
+        check(lib.hpt_checkpoint_bytes(self.h, ctypes.byref(n)), "hpt_checkpoint_bytes")
+        return n.value
+
+    @staticmethod
+    def _buffer(buf):
+        # (pointer, bytes, where) of a torch uint8 tensor (device or host) or a numpy uint8 array
+        if isinstance(buf, np.ndarray):
+            if buf.dtype != np.uint8 or not buf.flags["C_CONTIGUOUS"]:
+                raise ValueError("checkpoint buffer: contiguous uint8 array")
+            return buf.ctypes.data, buf.nbytes, HPT_MEM_HOST
+        if buf.dtype.itemsize != 1 or not buf.is_contiguous():
+            raise ValueError("checkpoint buffer: contiguous uint8 tensor")
+        return buf.data_ptr(), buf.numel(), HPT_MEM_DEVICE if buf.is_cuda else HPT_MEM_HOST
+
+    def save_checkpoint(self, buf=None):
+        """Write the state image into buf (torch uint8 tensor on the device or
+        host, or numpy uint8 array); a new numpy array when buf is None."""
+        if buf is None:
+            buf = np.zeros(self.checkpoint_bytes(), dtype=np.uint8)
+        ptr, n, where = self._buffer(buf)
+        check(lib.hpt_checkpoint_save(self.h, ctypes.c_void_p(ptr), n, where), "hpt_checkpoint_save")
+        return buf
+
+    def load_checkpoint(self, buf):
+        ptr, n, where = self._buffer(buf)
+        check(lib.hpt_checkpoint_load(self.h, ctypes.c_void_p(ptr), n, where), "hpt_checkpoint_load")
+
+    def phase_timing(self, enable=True):
+        check(lib.hpt_phase_timing(self.h, 1 if enable else 0), "hpt_phase_timing")
+
+    def phase_read(self):
+        out = (ctypes.c_double * 7)()
+        check(lib.hpt_phase_read(self.h, out), "hpt_phase_read")
+        return dict(gate_ms=out[0], gauge_ms=out[1], meas_ms=out[2], layers=int(out[3]),
+                    gauge_sweeps=int(out[4]), measurements=int(out[5]), meas_sweeps=int(out[6]))
+
     def _deg(self, v):
         Lx, Ly = self.cfg.Lx, self.cfg.Ly
         x, y = v % Lx, v // Lx
         return (y > 0) + (y < Ly - 1) + (x > 0) + (x < Lx - 1)
+
+
+def gram64_workspace_bytes(m, n):
+    out = ctypes.c_uint64()
+    check(lib.hpt_gram64_workspace_bytes(m, n, ctypes.byref(out)), "hpt_gram64_workspace_bytes")
+    return out.value
+
+
+def gram64(X, G, workspace=None, stream=None):
+    """G (float64, n x n) = X^T X for a float32 device matrix X viewed
+    column-major as X.shape = (n, ldx) row-major storage, i.e. X[j] is column
+    j of length m = ldx (hpt_gram64).  workspace: uint8 device tensor of at
+    least gram64_workspace_bytes(m, n) bytes; allocated here when None."""
+    import torch
+    n, m = X.shape
+    if X.dtype != torch.float32 or G.dtype != torch.float64 or not X.is_contiguous() or not G.is_contiguous():
+        raise ValueError("gram64: contiguous float32 X and float64 G")
+    if workspace is None:
+        workspace = torch.empty(max(gram64_workspace_bytes(m, n), 1), dtype=torch.uint8, device=X.device)
+    st = stream if stream is not None else torch.cuda.current_stream(X.device).cuda_stream
+    check(lib.hpt_gram64(ctypes.c_void_p(X.data_ptr()), m, n, m, ctypes.c_void_p(G.data_ptr()), G.shape[1],
+                         ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.c_void_p(st)), "hpt_gram64")
 
 
 def permute(src, dst, perm, stream=None):

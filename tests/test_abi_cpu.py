@@ -74,3 +74,25 @@ def test_required_bytes_fit_the_large_instance(hpt):
 def test_strerror(hpt):
     assert hpt.lib.hpt_strerror(-2).decode() == "arena too small"
     assert hpt.lib.hpt_strerror(0).decode() == "ok"
+
+
+def test_gram64_workspace_and_argument_checks_without_gpu(hpt):
+    # 10^6 x 400 (an interior site at chi = 100): 32 row splits of 400^2 doubles
+    assert hpt.gram64_workspace_bytes(10 ** 6, 400) == 32 * 400 * 400 * 8
+    assert hpt.gram64_workspace_bytes(1000, 0) == 0
+    assert hpt.gram64_workspace_bytes(10, 3) == 3 * 3 * 8
+    assert hpt.gram64_workspace_bytes(10 ** 7, 2000) <= hpt_part_max()
+    P = ctypes.c_void_p
+    # every refusal happens before any launch
+    assert hpt.lib.hpt_gram64(P(16), -1, 3, 4, P(16), 3, P(16), 1 << 20, None) == -1
+    assert hpt.lib.hpt_gram64(P(16), 8, 3, 4, P(16), 3, P(16), 1 << 20, None) == -1
+    assert hpt.lib.hpt_gram64(P(16), 8, 3, 8, P(16), 2, P(16), 1 << 20, None) == -1
+    assert hpt.lib.hpt_gram64(None, 8, 3, 8, P(16), 3, P(16), 1 << 20, None) == -1
+    assert hpt.lib.hpt_gram64(P(16), 8, 3, 8, P(16), 3, P(16), 8, None) == -2
+    assert hpt.lib.hpt_gram64(P(16), 8, 0, 8, None, 0, None, 0, None) == 0
+
+
+def hpt_part_max():
+    hdr = open(os.path.join(ROOT, "include", "hpt.h")).read()
+    m = re.search(r"#define HPT_GRAM64_PART_MAX \((\d+)ull << (\d+)\)", hdr)
+    return int(m.group(1)) << int(m.group(2))

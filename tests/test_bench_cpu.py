@@ -45,3 +45,16 @@ def test_roofline_peak_per_kind():
     assert bench.roofline_peak("mode", "fp64") == 78.6
     assert abs(bench.roofline_peak("bsplit", "bf16x6") - 2500.0 / 6) < 1e-9
 
+
+
+def test_bond_classes_of_the_10x10_lattice():
+    sys.path.insert(0, ROOT)
+    import bench
+    cl = bench.bond_classes(10)
+    assert {k: len(v) for k, v in cl.items()} == {"interior-interior": 112, "interior-edge": 32,
+                                                  "edge-edge": 28, "corner": 8}
+    assert sorted(sum(cl.values(), [])) == list(range(180))
+    cb = bench.centre_bonds(10)
+    assert len(cb) == 4
+    # horizontal bonds ((3,4),(4,4)) and ((4,4),(5,4)); vertical ((4,3),(4,4)) and ((4,4),(4,5))
+    assert cb == [4 * 9 + 3, 4 * 9 + 4, 90 + 3 * 10 + 4, 90 + 4 * 10 + 4]

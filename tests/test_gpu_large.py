@@ -1,8 +1,7 @@
 """The FP32-MFMA form against the FP64 form on the 10x10 chi = 100
 workload (dt = 0.05, the benchmark's BP settings, the FP32 form's
-truncation cutoff in both): |dC(t)| per layer.  Both
-runs together take several minutes of GPU time and 110 + 217 GB of HBM (one
-after the other), so the test is marked slow (HPT_SLOW=1).  Layers where
+truncation cutoff in both): |dC(t)| per layer.  The runs take about three
+minutes of GPU time and 110 + 217 GB of HBM (one after the other).  Layers where
 either measurement BP did not converge are reported, not compared (the
 method's own non-convergence, flagged by the library)."""
 
@@ -15,7 +14,7 @@ import pytest
 
 from tests.gpu_util import load_hpt
 
-pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+pytestmark = pytest.mark.gpu
 
 CFG = dict(Lx=10, Ly=10, chi_max=100, dt=0.05, J=1.0, h=1.0, bp_tol=1e-5, bp_max_sweeps=100,
            bp_init="warm", meas_tol=1e-10, meas_max_sweeps=400)
