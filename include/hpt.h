@@ -295,6 +295,22 @@ int hpt_gram64_workspace_bytes(int64_t m, int32_t n, uint64_t* bytes);
 int hpt_gram64(const float* X, int64_t m, int32_t n, int64_t ldx, double* G, int64_t ldg, void* workspace,
                uint64_t workspace_bytes, void* hip_stream);
 
+/* hpt_gram64 without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and errors as hpt_gram64, except
+ * that the per-split partial tiles live in a file-scope device array of
+ * HPT_GRAM64_PART_MAX bytes inside the library (one per GPU, held until the
+ * process ends; its address is looked up once per device on the first call,
+ * with that device current).  The call allocates nothing.  Sizes with
+ * n > HPT_GRAM64_NOALLOC_MAX_N (one split of n^2 doubles would not fit) return
+ * HPT_EINVAL before any launch.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads) race
+ * and must be serialised by the caller; calls ordered on one stream are safe.
+ * The array holds the last call's partials; nothing needs clearing. */
+#define HPT_GRAM64_NOALLOC_MAX_N 2896
+int hpt_gram64_noalloc(const float* X, int64_t m, int32_t n, int64_t ldx, double* G, int64_t ldg,
+                       void* hip_stream);
+
 /* Permute a column-major tensor on the device (Sec. "GPU Tensor Permutation").
  * in/out: device pointers, not overlapping; ndim <= 8; dims of the input;
  * perm[k] = input axis that becomes output axis k; elem_size 4 or 8.

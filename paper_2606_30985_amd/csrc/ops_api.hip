@@ -2,12 +2,42 @@
 // caller device buffers (no simulator handle): the float64 Gram of the
 // CholeskyQR first pass (Sec. "Adaptive QR Decomposition", Eq. cholqr).
 #include <cstdint>
+#include <mutex>
 
 #include "../../include/hpt.h"
 #include "common.h"
 
+// Scratch of hpt_gram64_noalloc: the per-split partial tiles live in this
+// file-scope device array (one copy per GPU, held until the process ends)
+// instead of a caller workspace.  Host code never passes the symbol itself to
+// a kernel: it uses the device address from hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[HPT_GRAM64_PART_MAX / 8];
+
 namespace hpt {
 namespace {
+
+// device address of `scratch` on each GPU, looked up once per device with
+// that device current (its first hpt_gram64_noalloc call)
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_on_current_device(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return HPT_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_hip_error(e, "hipGetSymbolAddress(scratch)");
+      return HPT_EHIP;
+    }
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HPT_OK;
+}
 
 // shared argument checks; *splits receives the row-split count
 int gram64_args(const float* X, int64_t m, int32_t n, int64_t ldx, const double* G, int64_t ldg, int* splits) {
@@ -42,6 +72,19 @@ int hpt_gram64(const float* X, int64_t m, int32_t n, int64_t ldx, double* G, int
   const uint64_t need = (uint64_t)splits * n * n * 8;
   if (!workspace || workspace_bytes < need) return HPT_ENOMEM;
   if (gram64_launch(X, ldx, (int)m, n, G, ldg, splits, (double*)workspace, (hipStream_t)hip_stream)) return HPT_EHIP;
+  return HPT_OK;
+}
+
+int hpt_gram64_noalloc(const float* X, int64_t m, int32_t n, int64_t ldx, double* G, int64_t ldg,
+                       void* hip_stream) {
+  int splits = 0;
+  const int r = gram64_args(X, m, n, ldx, G, ldg, &splits);
+  if (r || n == 0) return r;
+  if ((uint64_t)splits * n * n * 8 > HPT_GRAM64_PART_MAX) return HPT_EINVAL;   // n > HPT_GRAM64_NOALLOC_MAX_N
+  double* part = nullptr;
+  const int rs = scratch_on_current_device(&part);
+  if (rs) return rs;
+  if (gram64_launch(X, ldx, (int)m, n, G, ldg, splits, part, (hipStream_t)hip_stream)) return HPT_EHIP;
   return HPT_OK;
 }
 

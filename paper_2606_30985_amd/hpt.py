@@ -109,6 +109,7 @@ def _load():
         "hpt_phase_read": [P, ctypes.POINTER(dbl)],
         "hpt_gram64_workspace_bytes": [ctypes.c_int64, i32, ctypes.POINTER(u64)],
         "hpt_gram64": [P, ctypes.c_int64, i32, ctypes.c_int64, P, ctypes.c_int64, P, u64, P],
+        "hpt_gram64_noalloc": [P, ctypes.c_int64, i32, ctypes.c_int64, P, ctypes.c_int64, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -130,7 +131,7 @@ EXPORTED = ["hpt_config_default", "hpt_required_bytes", "hpt_state_bytes", "hpt_
             "hpt_get_meas_messages", "hpt_destroy", "hpt_strerror", "hpt_last_hip_error",
             "hpt_permute", "hpt_profile_gemm", "hpt_profile_gemm_read", "hpt_profile_read", "hpt_run_batch",
             "hpt_checkpoint_bytes", "hpt_checkpoint_save", "hpt_checkpoint_load", "hpt_phase_timing",
-            "hpt_phase_read", "hpt_gram64_workspace_bytes", "hpt_gram64"]
+            "hpt_phase_read", "hpt_gram64_workspace_bytes", "hpt_gram64", "hpt_gram64_noalloc"]
 
 HPT_MEM_HOST = 0
 HPT_MEM_DEVICE = 1
