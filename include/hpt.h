@@ -45,7 +45,8 @@ extern "C" {
 #define HPT_EINVAL   -1   /* bad argument: dims, centre, dt == 0, chi_max < 1, bond/site index */
 #define HPT_ENOMEM   -2   /* arena smaller than hpt_required_bytes, checked before any launch */
 #define HPT_EHIP     -3   /* HIP runtime error; hpt_last_hip_error() has its text */
-#define HPT_ENUMERIC -4   /* non-finite data, zero bond matrix, SVD non-convergence */
+#define HPT_ENUMERIC -4   /* non-finite data (host tensors given to a set call, bond
+                                 matrices, gate errors), zero bond matrix */
 #define HPT_ESTATE   -5   /* call order (e.g. library not initialised) */
 
 /* precision */
@@ -66,6 +67,8 @@ extern "C" {
 /* BP initialisation */
 #define HPT_BP_UNIFORM 0      /* gauge messages I/sqrt(chi) at the start of every layer */
 #define HPT_BP_WARM    1      /* continue from the messages left by the gates */
+#define HPT_BP_LEARNED 2      /* meas_init only: measurement messages proposed by the
+                                 warm-start network of hpt_set_meas_model */
 
 /* measurement flags */
 #define HPT_FLAG_BP_NOT_CONVERGED_GAUGE (1u << 0)
@@ -80,6 +83,7 @@ extern "C" {
 #define HPT_FLAG_TRAP_UNRESOLVED        (1u << 10) /* a verified trap was retried without success */
 #define HPT_FLAG_QR_RANK_DEFICIENT      (1u << 8)  /* a QR block had numerically dependent columns
                                                       (deflated by the pivoted Cholesky) */
+#define HPT_FLAG_SVD_NOT_CONVERGED      (1u << 11) /* an R-core SVD reached svd_max_sweeps */
 
 typedef struct {
   int32_t Lx, Ly;          /* lattice, >= 1 each, Lx*Ly >= 2 */
@@ -119,8 +123,25 @@ typedef struct {
   int32_t reserved0;
   double  trap_alpha;      /* damping of the retry; <= 0 (default): 0.5 when the measurement
                               damping is >= 1, else 0.8 */
-  int32_t reserved[4];
+  int32_t model_axes;      /* HPT_AXES_PAPER (default): H = -J sum XX - h sum Z (Eq.
+                              hamiltonian), observable Z_c.  HPT_AXES_ZZX: H = -J sum ZZ
+                              - h sum X, observable Z_c; computed as the paper's model
+                              conjugated by a Hadamard on every site (same gates and
+                              splitting, observable X_c) */
+  int32_t svd_max_sweeps;  /* sweep cap of the R-core Jacobi SVDs; 0 (default): 20 for the
+                              block Jacobi, 60 for the one-sided Jacobi.  A core that has
+                              not converged within the cap keeps its last iterate and sets
+                              HPT_FLAG_SVD_NOT_CONVERGED */
+  int32_t meas_init;       /* HPT_BP_UNIFORM (default): measurement messages 1/sqrt(chi);
+                              HPT_BP_LEARNED: warm start proposed by the network given with
+                              hpt_set_meas_model (one extra sweep, counted in meas_sweeps,
+                              computes its features) */
+  int32_t reserved[1];
 } hpt_config;
+
+/* model axes */
+#define HPT_AXES_PAPER 0
+#define HPT_AXES_ZZX   1
 
 typedef struct {
   int32_t  step;               /* layers applied since reset */
@@ -189,10 +210,12 @@ int hpt_get_site_tensor(hpt_sim* sim, int32_t site, double* host, uint64_t n, in
 
 /* Replace a site tensor; dims gives the chi of each present leg in U,D,L,R
  * order followed by 4.  Every bond's chi must agree with both end sites
- * before the next step: setting a tensor sets the chi of its bonds. */
+ * before the next step: setting a tensor sets the chi of its bonds.
+ * HPT_ENUMERIC (nothing changed) when an entry is not finite. */
 int hpt_set_site_tensor(hpt_sim* sim, int32_t site, const double* host, const int32_t* dims);
 
-/* Gauge message on bond/dir as a chi x chi column-major float64 matrix. */
+/* Gauge message on bond/dir as a chi x chi column-major float64 matrix
+ * (set: HPT_ENUMERIC, nothing changed, when an entry is not finite). */
 int hpt_get_messages(hpt_sim* sim, int32_t bond, int32_t dir, double* host, int32_t cap);
 int hpt_set_messages(hpt_sim* sim, int32_t bond, int32_t dir, const double* host, int32_t chi);
 
@@ -244,6 +267,52 @@ int hpt_checkpoint_load(hpt_sim* sim, const void* buf, uint64_t bytes, int32_t w
  * gauge sweeps, measurements, measurement sweeps}. */
 int hpt_phase_timing(hpt_sim* sim, int32_t enable);
 int hpt_phase_read(hpt_sim* sim, double* out7);
+
+/* Learned warm start of the measurement BP (an addition to the paper's method:
+ * uniform-start BP stays the default and the reference; Sec. "BP Fixed-Point
+ * Multiplicity" shows that the start decides which fixed point BP reaches).
+ * A two-layer perceptron applied to every component k of every directed
+ * message u -> v proposes a correction y to a base message:
+ *   x (HPT_LEARN_FEATURES floats) = (base_k, one_k, prev_k, [k < chi_prev],
+ *     sqrt(chi) lambda_k, k / chi, 1 / sqrt(chi), deg(u) / 4, [u = observable
+ *     site], dist(u, c) / (Lx + Ly), dist(v, c) - dist(u, c), h dt, J dt, t,
+ *     log chi / log chi_max, 0)
+ *   one = the outgoing message after one sweep from the uniform start,
+ *   prev = the previous hpt_measure's converged message on the same bond (its
+ *   first chi_prev entries), both L2-normalised with a non-negative sum;
+ *   base = prev_k where k < chi_prev, else one_k;
+ *   y = w2 . tanh(W1 x + b1) + b2 with W1, w2 and x rounded to BF16, sums in
+ *   float32; the warm message is normalise(base + y).
+ * Rows are ordered by bond, then direction (0: v1 -> v2), then k.
+ * Parameters: HPT_LEARN_PARAMS floats, device: W1 (HPT_LEARN_HIDDEN x
+ * HPT_LEARN_FEATURES, row-major), b1, w2 (HPT_LEARN_HIDDEN each), b2.
+ *
+ * hpt_meas_learn_rows: row count for the current bond dimensions.
+ * hpt_meas_features: X (rows x HPT_LEARN_FEATURES) and base (rows) of the
+ *   current state, device buffers of cap rows (HPT_ENOMEM if short); runs the
+ *   one sweep, leaves the previous measurement's messages in place.  Syncs.
+ * hpt_meas_targets: after hpt_measure at the same state, T = m - base for the
+ *   converged messages m (normalised as above).  Syncs.
+ * hpt_set_meas_model: parameters (device, caller-owned, read at every
+ *   hpt_measure with meas_init = HPT_BP_LEARNED; HPT_ESTATE there when null).
+ * hpt_learn_forward: y (rows) for X (rows x HPT_LEARN_FEATURES), device.
+ * hpt_learn_backward: grad (HPT_LEARN_PARAMS + 1 floats, device) = gradient of
+ *   L = sum_r (y_r - t_r)^2 / rows, then L; fixed summation order.
+ * hpt_learn_adam: one Adam step (beta 0.9, 0.999, eps 1e-8) at step >= 1 on
+ *   params with moments m, v (HPT_LEARN_PARAMS floats each, device).
+ * All stream-ordered on hip_stream (the handle's stream for the hpt_meas_*). */
+#define HPT_LEARN_FEATURES 16
+#define HPT_LEARN_HIDDEN   128
+#define HPT_LEARN_PARAMS   (HPT_LEARN_HIDDEN * HPT_LEARN_FEATURES + 2 * HPT_LEARN_HIDDEN + 1)
+int hpt_meas_learn_rows(hpt_sim* sim, int64_t* rows);
+int hpt_meas_features(hpt_sim* sim, float* X, float* base, int64_t cap);
+int hpt_meas_targets(hpt_sim* sim, const float* base, float* T, int64_t cap);
+int hpt_set_meas_model(hpt_sim* sim, const float* params);
+int hpt_learn_forward(const float* params, const float* X, int64_t rows, float* y, void* hip_stream);
+int hpt_learn_backward(const float* params, const float* X, const float* y, const float* t, int64_t rows,
+                       float* grad, void* hip_stream);
+int hpt_learn_adam(float* params, float* m, float* v, const float* grad, int32_t step, float lr,
+                   void* hip_stream);
 
 int hpt_destroy(hpt_sim* sim);
 

@@ -36,8 +36,8 @@ def all_coefficients(net):
 
 
 def pinned_contraction(net, centre=None):
-    """Exact C = coefficient of (Z at centre, I elsewhere)."""
+    """Exact C = coefficient of (the observable's Pauli at centre, I elsewhere)."""
     c = net.centre if centre is None else centre
-    T = [net.psi[v][..., 3 if v == c else 0] for v in range(net.lat.n_sites)]
+    T = [net.psi[v][..., net.obs_p if v == c else 0] for v in range(net.lat.n_sites)]
     sub = _subscripts(net, False)
     return float(np.einsum(sub, *T, optimize="greedy"))

@@ -81,6 +81,8 @@ class Config:
     trap_sweeps: int = 30                 # trap-candidate threshold (sweeps)
     trap_retry: bool = False              # remediate verified traps (run.remediate_trap)
     trap_alpha: Optional[float] = None    # damping of the retry; None -> paper's rule
+    model_axes: str = "paper"             # "paper": H = -J sum XX - h sum Z, observable Z_c (Eq.
+                                          # hamiltonian); "zzx": H = -J sum ZZ - h sum X, observable Z_c
 
 
 # --------------------------------------------------------------------------
@@ -164,6 +166,14 @@ class OperatorNetwork:
         self.cfg = cfg
         self.lat = Lattice(cfg.Lx, cfg.Ly)
         self.centre = self.lat.centre() if cfg.centre is None else cfg.centre
+        # The ZZ-coupling, X-field model is the paper's model conjugated by a
+        # Hadamard on every site: H_zzx = W H W with W = prod_v Hd_v, and its
+        # observable Z_c maps to W Z_c W = X_c.  So its C(t) is the paper-frame
+        # network started from X_c and pinned on X at the observable site; the
+        # gates (and their Trotter splitting) are the paper's.
+        if cfg.model_axes not in ("paper", "zzx"):
+            raise ValueError("model_axes is 'paper' or 'zzx'")
+        self.obs_p = 3 if cfg.model_axes == "paper" else 1
         self.G1 = field_ptm(cfg.h, cfg.dt)
         self.G2 = coupling_ptm(cfg.J, cfg.dt)
         self.reset()
@@ -176,7 +186,7 @@ class OperatorNetwork:
         self.psi = []
         for v in range(lat.n_sites):
             T = np.zeros((1,) * lat.degree(v) + (4,))
-            T[(0,) * lat.degree(v) + (3 if v == self.centre else 0,)] = 1.0
+            T[(0,) * lat.degree(v) + (self.obs_p if v == self.centre else 0,)] = 1.0
             self.psi.append(T)
         self.M = [[np.ones((1, 1)), np.ones((1, 1))] for _ in range(lat.n_bonds)]
         self.lam = [np.ones(1) for _ in range(lat.n_bonds)]
@@ -337,7 +347,7 @@ class OperatorNetwork:
     def pinned(self):
         out = []
         for v in range(self.lat.n_sites):
-            p = 3 if v == self.centre else 0
+            p = self.obs_p if v == self.centre else 0
             out.append(self.psi[v][..., p])
         return out
 

@@ -76,6 +76,15 @@ int gemm_profile_active();
 int mode_product_f32(const float* S, const float* src, float* dst, int n, int64_t inner, int64_t outer,
                      hipStream_t s);
 
+// Mode product of float32 data with a float64 factor in float64 arithmetic:
+// dst[a, j, b] = sum_k S[j, k] src[a, k, b] (S n x n column-major), float64
+// products and sums in increasing k, each result rounded once to float32.
+// For the environment factors of the float32 form's Householder route, whose
+// absorb/deabsorb pair must multiply to the projector to float64 accuracy.
+// Returns 0, or < 0 on a HIP error / bad size.
+int mode_product_f64acc(const double* S, const float* src, float* dst, int n, int64_t inner, int64_t outer,
+                        hipStream_t s);
+
 // Leg Gram of the float32 form: out[i, j] (n x n, float64) = sum over a < inner,
 // b < outer of psi[a, i, b] cur[a, j, b] (column-major), float32 MFMA products
 // accumulated per workgroup, float64 partials (part, n^2 per workgroup, at

@@ -9,6 +9,7 @@
 #include "linalg.h"
 #include "misc.h"
 #include "rcore.h"
+#include "learn.h"
 
 namespace hpt {
 
@@ -38,6 +39,7 @@ struct Carve {
   uint64_t chol;    // CholeskyQR2 scratch
   uint64_t small;   // scalars, bethe vectors, result arrays
   uint64_t jobs; uint64_t jobs_bytes;
+  uint64_t learn; int64_t learn_rows;   // learned warm start: X, base, y, prev messages, Vidal values
   uint64_t total;
 };
 
@@ -79,6 +81,7 @@ struct BondSlot {
 struct hpt_sim {
   hpt_config cfg;
   int N, nb, centre, chi_max;
+  int obs_p;        // Pauli index of the observable at the centre (3 = Z; 1 = X for HPT_AXES_ZZX)
   bool fp32;
   bool bsplit;   // the split-bf16 form of the float32 GEMMs
   int elem;
@@ -132,6 +135,14 @@ struct hpt_sim {
   // last measurement (step, C, gate error) and the one of the layer before
   int rec_step, prv_step;
   double rec_C, rec_gate_err, prv_C, prv_gate_err;
+  // learned warm start of the measurement BP
+  float* lX;                    // learn_rows x LEARN_F features
+  float* lbase;                 // learn_rows
+  float* ly;                    // learn_rows
+  double* lprev;                // copy of the previous measurement's messages (2 nb chi_max)
+  double* llam;                 // Vidal values of every bond (nb chi_max)
+  const float* meas_model;      // caller's parameters (LEARN_P floats, device) or null
+  std::vector<int> meas_chi;    // chi of each bond at the last measurement (0: none)
   // per-phase timing (hpt_phase_timing): HIP events on the handle's stream
   bool phase_on;
   hipEvent_t phase_ev[5];

@@ -16,6 +16,7 @@
 #include <string>
 #include <thread>
 #include <atomic>
+#include <type_traits>
 #include <vector>
 
 #include "engine.h"
@@ -93,6 +94,9 @@ int validate(const hpt_config* c) {
   if (c->trap_retry != 0 && c->trap_retry != 1) return HPT_EINVAL;
   if (c->trap_alpha > 1.0 || c->trap_sweeps < 1) return HPT_EINVAL;
   if (c->bp_init != HPT_BP_UNIFORM && c->bp_init != HPT_BP_WARM) return HPT_EINVAL;
+  if (c->meas_init != HPT_BP_UNIFORM && c->meas_init != HPT_BP_LEARNED) return HPT_EINVAL;
+  if (c->model_axes != HPT_AXES_PAPER && c->model_axes != HPT_AXES_ZZX) return HPT_EINVAL;
+  if (c->svd_max_sweeps < 0) return HPT_EINVAL;
   // the storage of one interior site must stay addressable with 64-bit offsets
   // and its element count below 2^40
   const int maxdeg = (c->Lx >= 3 && c->Ly >= 3) ? 4 : ((c->Lx >= 3 || c->Ly >= 3) ? 3 : 2);
@@ -245,6 +249,10 @@ void make_carve(const hpt_config& c, Carve& cv) {
                                  (uint64_t)mcb * sizeof(BondCore));
   cv.jobs_bytes = 4ull << 20;
   cv.jobs = off; off = align_up(off + cv.jobs_bytes);
+  cv.learn_rows = 2ll * nb * C;
+  cv.learn = off;
+  off = align_up(off + (uint64_t)cv.learn_rows * (LEARN_F + 2) * 4);
+  off = align_up(off + (uint64_t)cv.learn_rows * 8 + (uint64_t)nb * C * 8);
   cv.total = off;
 }
 
@@ -430,6 +438,9 @@ struct SitePlan {
   int k;
   int deferred;     // float32 form: Gram taken, CholeskyQR2 algebra pending
   int was_deferred;
+  int pinv_cut;     // an environment eigenvalue of this site was dropped
+  int direct;       // float32 form, direct route: the storage holds the permuted,
+                    // unabsorbed psi and the reconstruction multiplies it (no deabsorb)
 };
 
 template <typename T>
@@ -442,12 +453,109 @@ const double* env_S<double>(BondSlot& sl, int i, int e, bool inv) { return inv ?
 template <>
 const float* env_S<float>(BondSlot& sl, int i, int e, bool inv) { return inv ? sl.Sinv32[i][e] : sl.S32[i][e]; }
 
+// Environment factor (sqrt(M) when inv is false, its pseudo-inverse when
+// true) on one axis.  Float64 form: MFMA products in float64.  Float32 form:
+// float64 factors in float64 arithmetic on the float32 data, so that an
+// absorb/deabsorb pair multiplies to the projector to float64 accuracy.
+template <typename T>
+int env_product(hpt_sim* s, const T* src, T* dst, const int64_t* dims, int nd, int axis, BondSlot& sl, int i, int e,
+                bool inv) {
+  if constexpr (std::is_same<T, float>::value) {
+    int64_t inner = 1, outer = 1;
+    for (int q = 0; q < axis; ++q) inner *= dims[q];
+    for (int q = axis + 1; q < nd; ++q) outer *= dims[q];
+    KR(mode_product_f64acc(inv ? sl.Sinv[i][e] : sl.S[i][e], src, dst, (int)dims[axis], inner, outer, s->stream));
+    return 0;
+  } else {
+    return mode_product<T>(s, src, dst, dims, nd, axis, env_S<T>(sl, i, e, inv));
+  }
+}
+
+// dims of a site tensor with the cut leg moved next to the Pauli leg
+void permuted_dims(const SitePlan& P, int64_t* pd) {
+  int q = 0;
+  for (int l = 0; l < P.deg; ++l)
+    if (l != P.cut) pd[q++] = P.dims[l];
+  pd[q++] = P.dims[P.cut];
+  pd[q] = 4;
+}
+
+// Float32 form, direct route (a tall block for CholeskyQR2 and no environment
+// eigenvalue dropped): Xraw = psi with the cut leg moved next to the Pauli leg
+// is kept in the site's storage; its absorbed copy X = Xraw x_e sqrt(M_e)
+// (float32 MFMA products) lives in a temporary only for the float64 Gram
+// G1 = X^T X and the sign projection.  The reconstruction later multiplies
+// Xraw itself: the environment products act on the rows of X and the
+// reconstruction W on its columns, so (X W) x_e sqrt(M_e)^-1 = Xraw W
+// exactly, and no deabsorb is needed.  (A float32 deabsorb factor would leave
+// sqrt(M) sqrt(M)^-1 = 1 + O(eps32) on every environment leg of every gate, a
+// coherent error that moves C(t) by a few 1e-6 over a 10x10 run.)
+int phase_a_direct(hpt_sim* s, int i, BondSlot& sl, SitePlan& P) {
+  float* psi = psi_of<float>(s, P.v);
+  const int n = (int)P.n;
+  const int64_t m = P.m;
+  int64_t pd[5];
+  permuted_dims(P, pd);
+  float* xraw = psi;
+  const bool need_perm = P.cut != P.deg - 1;
+  if (need_perm) {
+    int64_t A = 1, Cc = 1;
+    for (int l = 0; l < P.cut; ++l) A *= P.dims[l];
+    for (int l = P.cut + 1; l < P.deg; ++l) Cc *= P.dims[l];
+    xraw = (float*)s->t[2];
+    KR(permute_swap_mid(psi, xraw, A, P.dims[P.cut], Cc, 4, (int)sizeof(float), s->stream));
+  }
+  const float* X = xraw;
+  int ti = 0;
+  for (int e = 0; e < P.nenv; ++e) {
+    float* dst = (float*)s->t[ti];
+    ti ^= 1;
+    RC(mode_product<float>(s, X, dst, pd, P.deg + 1, e, sl.S32[i][e]));
+    X = dst;
+  }
+  RC(gram<float>(s, n, m, X, m, sl.qa[i][0]));
+  if (i == 0) KR(launch_sign_projection<float>(X, m, m, n, sl.z, s->part, s->cv.part_cap, s->stream));
+  if (need_perm) HPT_HIP(hipMemcpyAsync(psi, xraw, sizeof(float) * m * n, hipMemcpyDeviceToDevice, s->stream));
+  P.direct = 1;
+  P.deferred = 1;
+  P.was_deferred = 1;
+  return 0;
+}
+
+// A direct-route block whose CholeskyQR2 failed goes to Householder: absorb
+// its environment in place (float64 factors), after which the block is an
+// ordinary one (Q of X, deabsorb after the reconstruction).
+int direct_to_framed(hpt_sim* s, int i, BondSlot& sl, SitePlan& P) {
+  float* psi = psi_of<float>(s, P.v);
+  int64_t pd[5];
+  permuted_dims(P, pd);
+  const float* src = psi;
+  int ti = 0;
+  for (int e = 0; e < P.nenv; ++e) {
+    float* dst = (float*)s->t[ti];
+    ti ^= 1;
+    RC(env_product<float>(s, src, dst, pd, P.deg + 1, e, sl, i, e, false));
+    src = dst;
+  }
+  if (src != psi) HPT_HIP(hipMemcpyAsync(psi, src, sizeof(float) * P.m * P.n, hipMemcpyDeviceToDevice, s->stream));
+  P.direct = 0;
+  return 0;
+}
+
 template <typename T>
 int phase_a_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, uint32_t& flags) {
   const BondInfo& bi = s->bonds[b];
   const T* S_unused = nullptr;
   (void)S_unused;
   T* psi = psi_of<T>(s, P.v);
+  P.direct = 0;
+  P.deferred = 0;
+  P.was_deferred = 0;
+  const bool tall = s->cfg.qr_mode == HPT_QR_ADAPTIVE && P.m >= (int64_t)s->cfg.chol_min_ratio * P.n &&
+                    P.n >= s->cfg.chol_min_cols;
+  if constexpr (std::is_same<T, float>::value) {
+    if (tall && !P.pinv_cut) return phase_a_direct(s, i, sl, P);
+  }
   // absorb sqrt of each environment message (mode products, ping-pong)
   int64_t dims[5];
   for (int l = 0; l <= P.deg; ++l) dims[l] = P.dims[l];
@@ -463,7 +571,7 @@ int phase_a_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, uint32_t& 
       dst = (T*)s->t[ti];
       ti ^= 1;
     }
-    RC(mode_product<T>(s, src, dst, dims, P.deg + 1, P.env_pos[e], env_S<T>(sl, i, e, false)));
+    RC(env_product<T>(s, src, dst, dims, P.deg + 1, P.env_pos[e], sl, i, e, false));
     src = dst;
   }
   // permute [A, cut, C, P] -> [A, C, cut, P] into the site's own storage
@@ -485,10 +593,7 @@ int phase_a_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, uint32_t& 
   const int64_t m = P.m;
   const int ldR = 4 * s->chi_max;
   P.chol = 0;
-  bool use_chol = s->cfg.qr_mode == HPT_QR_ADAPTIVE && m >= (int64_t)s->cfg.chol_min_ratio * n &&
-                  n >= s->cfg.chol_min_cols;
-  P.deferred = 0;
-  P.was_deferred = 0;
+  const bool use_chol = tall;
   if (use_chol && s->fp32) {
     // float32 form: only the Gram here; the float64 algebra of every block of
     // the colour runs batched afterwards
@@ -578,6 +683,12 @@ int phase_a_finish(hpt_sim* s, int i, BondSlot& sl, SitePlan& P) {
   T* psi = psi_of<T>(s, P.v);
   const int n = (int)P.n;
   const int64_t m = P.m;
+  if constexpr (std::is_same<T, float>::value) {
+    if (P.direct) {
+      if (P.chol) return 0;   // sign projection taken with the Gram
+      RC(direct_to_framed(s, i, sl, P));
+    }
+  }
   if (!P.chol) {
     if (std::min<int64_t>(m, n) > 1024) return HPT_EINVAL;
     QrJob<T> qj{psi, m, (int)m, n, sl.R[i], 4 * s->chi_max, s->R1 /* tau scratch */, 1, nullptr, 0};
@@ -745,16 +856,25 @@ int phase_c_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, int cn) {
     int64_t A = 1, Cc = 1;
     for (int l = 0; l < P.cut; ++l) A *= dims[l];
     for (int l = P.cut + 1; l < P.deg; ++l) Cc *= dims[l];
-    T* dst = (T*)s->t[1];
+    // direct route: the reconstruction multiplied the unabsorbed psi, so the
+    // inverse permutation is the last step and lands in the site's storage
+    T* dst = P.direct ? psi : (T*)s->t[1];
     KR(permute_swap_mid(src, dst, A, Cc, cn, 4, (int)sizeof(T), s->stream));
+    if (P.direct) return 0;
     src = dst;
     ti = 0;
+  }
+  if (P.direct) {
+    int64_t total = 4;
+    for (int l = 0; l < P.deg; ++l) total *= dims[l];
+    HPT_HIP(hipMemcpyAsync(psi, src, sizeof(T) * total, hipMemcpyDeviceToDevice, s->stream));
+    return 0;
   }
   // deabsorb with the pseudo-inverse square roots; the last product lands in psi
   for (int e = 0; e < P.nenv; ++e) {
     const bool last = e == P.nenv - 1;
     T* dst = last ? psi : (T*)s->t[ti];
-    RC(mode_product<T>(s, src, dst, dims, P.deg + 1, P.env_pos[e], env_S<T>(sl, i, e, true)));
+    RC(env_product<T>(s, src, dst, dims, P.deg + 1, P.env_pos[e], sl, i, e, true));
     if (!last) {
       src = dst;
       ti ^= 1;
@@ -808,6 +928,21 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
     PsqJob* pjd;
     RC(stage(s, pj.data(), (int)pj.size(), &pjd));
     KR(launch_pseudo_sqrt(pjd, (int)pj.size(), s->cfg.eps_pinv, s->stream));
+  }
+  for (SitePlan& P : plans) P.pinv_cut = 0;
+  if (s->fp32 && !pj.empty()) {
+    // the route of each block depends on whether an environment eigenvalue
+    // was dropped (the direct route needs sqrt(M) invertible on every leg)
+    for (int q = 0; q < nb; ++q)
+      HPT_HIP(hipMemcpyAsync(s->hscratch + 64 * q, s->slots[q].ncut, 6 * sizeof(int), hipMemcpyDeviceToHost,
+                             s->stream));
+    RC(sync_stream(s));
+    for (int q = 0; q < nb; ++q) {
+      const int* nc = (const int*)(s->hscratch + 64 * q);
+      for (int i = 0; i < 2; ++i)
+        for (int e = 0; e < plans[2 * q + i].nenv; ++e)
+          if (nc[3 * i + e] != 0) plans[2 * q + i].pinv_cut = 1;
+    }
   }
   // phase A: absorb, permute, QR
   for (int q = 0; q < nb; ++q)
@@ -940,7 +1075,8 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
         j = SmallGemmJob{q1, q0, K, nullptr, nullptr, nullptr, bc.Tm[1], ldR, 0, bc.Tm[0], ldR, 1, bc.G, ldR, 1.0, 0.0, nullptr};
       gj.push_back(j);
       sj.push_back(SvdJob{bc.G, ldR, std::max(q0, q1), std::min(q0, q1), bc.V, ldR, bc.s, bc.perm,
-                          s->slots[q].svd_state + 4, s->slots[q].svd_state, (double*)(s->slots[q].svd_state + 8)});
+                          s->slots[q].svd_state + 4, s->slots[q].svd_state, (double*)(s->slots[q].svd_state + 8),
+                          s->cfg.svd_max_sweeps});
     }
     SmallGemmJob* gd;
     RC(stage(s, gj.data(), nb, &gd));
@@ -970,7 +1106,7 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
       SvdJob* sd;
       RC(stage(s, sj.data(), nb, &sd));
       KR(launch_block_jacobi_svd(sd, sj.data(), nb, s->stream, (int*)(s->res + 12),
-                                 (volatile int*)(s->hscratch + s->hscratch_bytes - 64)));
+                                 (volatile int*)(s->hscratch + s->hscratch_bytes - 64), s->cfg.svd_max_sweeps));
       KR(launch_rcore_precond_finish(cd, nb, s->stream));
       RC(stage(s, back.data(), nb, &gd));
       KR(launch_small_gemm(gd, back.data(), nb, s->stream));
@@ -1038,6 +1174,9 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
   for (int q = 0; q < nb; ++q)
     HPT_HIP(hipMemcpyAsync(s->hscratch + ncut_off + q * 64, s->slots[q].ncut, 6 * sizeof(int),
                            hipMemcpyDeviceToHost, s->stream));
+  for (int q = 0; q < nb; ++q)
+    HPT_HIP(hipMemcpyAsync(s->hscratch + ncut_off + q * 64 + 40, s->slots[q].svd_state + 3, sizeof(int),
+                           hipMemcpyDeviceToHost, s->stream));
   static const bool dbg_svd = getenv("HPT_DEBUG_SVD") != nullptr;
   if (dbg_svd)
     for (int q = 0; q < nb; ++q)
@@ -1065,6 +1204,7 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
         if (nc[3 * i + e] < 0) return HPT_ENUMERIC;
         if (nc[3 * i + e] > 0) flags |= HPT_FLAG_PINV_CUT;
       }
+    if (*(const int*)(s->hscratch + ncut_off + q * 64 + 40)) flags |= HPT_FLAG_SVD_NOT_CONVERGED;
     flags |= (uint32_t)bc.flags;
     s->layer_gate_err += bc.gate_err;
     s->lam[b].assign((const double*)(s->hscratch + lam_off + (uint64_t)q * C * 8),
@@ -1233,7 +1373,7 @@ int meas_outgoing(hpt_sim* s, bool only_first_leg) {
     site_dims(s, v, dims);
     int64_t slice = 1;
     for (int l = 0; l < si.deg; ++l) slice *= dims[l];
-    const int p = v == s->centre ? 3 : 0;
+    const int p = v == s->centre ? s->obs_p : 0;
     const T* Tv = psi_of<T>(s, v) + (int64_t)p * slice;
     const int L = si.deg - 1;
     const int64_t rows = slice / dims[L];
@@ -1303,12 +1443,95 @@ struct MeasResult {
   uint32_t flags;   // BETHE_ZERO only
 };
 
+int dist_to(hpt_sim* s, int v) {
+  const int Lx = s->cfg.Lx;
+  return std::abs(v % Lx - s->centre % Lx) + std::abs(v / Lx - s->centre / Lx);
+}
+
+// Features of the learned warm start (rows: directed bond (b, d), then
+// component k < chi_b): the previous measurement's messages are copied out,
+// one sweep runs from the uniform start, and the feature kernel reads the
+// copy, that sweep's outgoing messages and the Vidal values.  The messages
+// of the previous measurement are put back afterwards.  Returns the edges
+// through *edges_dev (staged) and the row count.
 template <typename T>
-int meas_bp_t(hpt_sim* s, double alpha, MeasResult& mr) {
-  const int nbd = 2 * s->nb;
+int learn_features(hpt_sim* s, LearnEdge** edges_dev, int64_t* rows_out) {
+  const int C = s->chi_max;
+  HPT_HIP(hipMemcpyAsync(s->lprev, s->mmsg, 2ull * s->nb * C * 8, hipMemcpyDeviceToDevice, s->stream));
+  // Vidal values through the pinned scratch (stream-ordered before any later
+  // device-to-host copy into it)
+  double* hl = (double*)s->hscratch;
+  for (int b = 0; b < s->nb; ++b)
+    for (int k = 0; k < C; ++k) hl[(int64_t)b * C + k] = k < (int)s->lam[b].size() ? s->lam[b][k] : 0.0;
+  HPT_HIP(hipMemcpyAsync(s->llam, hl, (uint64_t)s->nb * C * 8, hipMemcpyHostToDevice, s->stream));
   for (int b = 0; b < s->nb; ++b)
     for (int d = 0; d < 2; ++d)
       KR(launch_fill_value(mmsg_slot(s, b, d), s->chi[b], 1.0 / std::sqrt((double)s->chi[b]), s->stream));
+  RC(meas_outgoing<T>(s, false));
+  std::vector<LearnEdge> ed;
+  int64_t row = 0;
+  for (int b = 0; b < s->nb; ++b)
+    for (int d = 0; d < 2; ++d) {
+      const int u = d == 0 ? s->bonds[b].v1 : s->bonds[b].v2, v = d == 0 ? s->bonds[b].v2 : s->bonds[b].v1;
+      LearnEdge e;
+      e.prev = s->meas_chi[b] > 0 ? s->lprev + (uint64_t)(2 * b + d) * C : nullptr;
+      e.one = mmsg_hat_slot(s, b, d);
+      e.lam = s->llam + (uint64_t)b * C;
+      e.out = mmsg_slot(s, b, d);
+      e.chi = s->chi[b];
+      e.chi_prev = s->meas_chi[b];
+      e.row0 = row;
+      e.deg = (float)s->sites[u].deg;
+      e.obs = u == s->centre ? 1.0f : 0.0f;
+      e.dist = (float)dist_to(s, u) / (float)(s->cfg.Lx + s->cfg.Ly);
+      e.dir = (float)(dist_to(s, v) - dist_to(s, u));
+      ed.push_back(e);
+      row += s->chi[b];
+    }
+  if (row > s->cv.learn_rows) return HPT_ENOMEM;
+  LearnGlobals g;
+  g.h_dt = (float)(s->cfg.h * s->cfg.dt);
+  g.J_dt = (float)(s->cfg.J * s->cfg.dt);
+  g.t = (float)(s->step * s->cfg.dt);
+  g.inv_log_chimax = s->chi_max > 1 ? (float)(1.0 / std::log((double)s->chi_max)) : 0.0f;
+  RC(stage(s, ed.data(), (int)ed.size(), edges_dev));
+  KR(launch_learn_features(*edges_dev, (int)ed.size(), g, s->lX, s->lbase, s->stream));
+  *rows_out = row;
+  return 0;
+}
+
+// learned: warm start from the network; reuse: the features of the previous
+// call at this layer are still in the arena (rerun of the same BP)
+template <typename T>
+int meas_bp_t(hpt_sim* s, double alpha, MeasResult& mr, bool learned = false, bool reuse = false) {
+  const int nbd = 2 * s->nb;
+  int extra = 0;
+  if (learned) {
+    // warm start: m = normalise(base + y) with y the network's correction
+    LearnEdge* ed;
+    int64_t rows = 0;
+    if (reuse) {
+      std::vector<LearnEdge> e(nbd);
+      for (int b = 0; b < s->nb; ++b)
+        for (int d = 0; d < 2; ++d) {
+          std::memset(&e[2 * b + d], 0, sizeof(LearnEdge));
+          e[2 * b + d].out = mmsg_slot(s, b, d);
+          e[2 * b + d].chi = s->chi[b];
+          e[2 * b + d].row0 = rows;
+          rows += s->chi[b];
+        }
+      RC(stage(s, e.data(), nbd, &ed));
+    } else {
+      RC(learn_features<T>(s, &ed, &rows));
+    }
+    KR(launch_learn_forward(s->meas_model, s->lX, rows, s->ly, s->stream));
+    KR(launch_learn_warm(ed, nbd, s->lbase, s->ly, s->stream));
+    extra = 1;   // the sweep taken for the features is counted
+  } else {
+    for (int b = 0; b < s->nb; ++b)
+      for (int d = 0; d < 2; ++d)
+        KR(launch_fill_value(mmsg_slot(s, b, d), s->chi[b], 1.0 / std::sqrt((double)s->chi[b]), s->stream));
+  }
   std::vector<MeasNormJob> nj(nbd);
   for (int b = 0; b < s->nb; ++b)
     for (int d = 0; d < 2; ++d) nj[2 * b + d] = MeasNormJob{mmsg_slot(s, b, d), mmsg_hat_slot(s, b, d), s->chi[b]};
@@ -1355,8 +1578,9 @@ int meas_bp_t(hpt_sim* s, double alpha, MeasResult& mr) {
   } else {
     mr.logC = res[0]; mr.sign = res[1] < 0 ? -1 : 1; mr.C = mr.sign * std::exp(mr.logC);
   }
-  mr.sweeps = sweeps;
+  mr.sweeps = sweeps + extra;
   mr.delta = delta;
+  for (int b = 0; b < s->nb; ++b) s->meas_chi[b] = s->chi[b];
   return 0;
 }
 
@@ -1372,7 +1596,9 @@ int measure_t(hpt_sim* s, hpt_measurement* out) {
   }
   if (s->phase_on) HPT_HIP(hipEventRecord(s->phase_ev[3], s->stream));
   MeasResult mr;
-  RC(meas_bp_t<T>(s, alpha, mr));
+  const bool learned = s->cfg.meas_init == HPT_BP_LEARNED;
+  if (learned && !s->meas_model) return HPT_ESTATE;
+  RC(meas_bp_t<T>(s, alpha, mr, learned));
   uint32_t flags = s->layer_flags | mr.flags;
   if (mr.sweeps >= s->cfg.trap_sweeps && mr.delta < tol) flags |= HPT_FLAG_TRAP_CANDIDATE;
   // trap remediation (Sec. "BP Fixed-Point Multiplicity"): a candidate whose
@@ -1391,7 +1617,7 @@ int measure_t(hpt_sim* s, hpt_measurement* out) {
     } else {
       // the first value stands: rerun its BP (deterministic) so that the
       // measurement messages left in the handle are the ones of the reported C
-      RC(meas_bp_t<T>(s, alpha, mr));
+      RC(meas_bp_t<T>(s, alpha, mr, learned, true));
       flags |= HPT_FLAG_TRAP_UNRESOLVED;
     }
   }
@@ -1501,6 +1727,7 @@ void make_gate_tables(hpt_sim* s) {
 
 template <typename T>
 int reset_t(hpt_sim* s) {
+  s->meas_chi.assign(s->nb, 0);
   s->rec_step = s->prv_step = -1;
   s->rec_C = s->prv_C = s->rec_gate_err = s->prv_gate_err = 0.0;
   for (int b = 0; b < s->nb; ++b) {
@@ -1510,7 +1737,7 @@ int reset_t(hpt_sim* s) {
   for (int v = 0; v < s->N; ++v) {
     T* p = psi_of<T>(s, v);
     KR(launch_fill_t<T>(p, 4, 0.0, s->stream));
-    KR(launch_fill_t<T>(p + (v == s->centre ? 3 : 0), 1, 1.0, s->stream));
+    KR(launch_fill_t<T>(p + (v == s->centre ? s->obs_p : 0), 1, 1.0, s->stream));
   }
   for (int b = 0; b < s->nb; ++b)
     for (int d = 0; d < 2; ++d) KR(launch_fill_value(gmsg_slot(s, b, d), 1, 1.0, s->stream));
@@ -1602,6 +1829,9 @@ int hpt_create(const hpt_config* cfg, void* arena, uint64_t arena_bytes, void* h
   s->nb = (int)s->bonds.size();
   const int cx = cfg->cx < 0 ? (cfg->Lx - 1) / 2 : cfg->cx, cy = cfg->cy < 0 ? (cfg->Ly - 1) / 2 : cfg->cy;
   s->centre = cx + cfg->Lx * cy;
+  // HPT_AXES_ZZX is the paper's model conjugated by a Hadamard on every site:
+  // same gates, observable X_c (initial operator and pinned index at the centre)
+  s->obs_p = cfg->model_axes == HPT_AXES_ZZX ? 1 : 3;
   s->colour_bonds.assign(4, {});
   for (int b = 0; b < s->nb; ++b) s->colour_bonds[s->bonds[b].colour].push_back(b);
   s->chi.assign(s->nb, 1);
@@ -1661,9 +1891,21 @@ int hpt_create(const hpt_config* cfg, void* arena, uint64_t arena_bytes, void* h
     c = (char*)(((uintptr_t)c + 255) / 256 * 256);
     s->cores_dev = (BondCore*)c;
   }
+  {
+    char* c = A + s->cv.learn;
+    const int64_t R = s->cv.learn_rows;
+    s->lX = (float*)c; c += R * LEARN_F * 4;
+    s->lbase = (float*)c; c += R * 4;
+    s->ly = (float*)c; c += R * 4;
+    c = (char*)(((uintptr_t)c + 255) / 256 * 256);
+    s->lprev = (double*)c; c += R * 8;
+    s->llam = (double*)c;
+    s->meas_model = nullptr;
+  }
   s->jobs_dev = A + s->cv.jobs;
   s->jobs_used = 0;
-  s->hscratch_bytes = (uint64_t)s->cv.max_colour_bonds * (sizeof(BondCore) + s->chi_max * 8 + 64) + (1 << 20);
+  s->hscratch_bytes = (uint64_t)s->cv.max_colour_bonds * (sizeof(BondCore) + s->chi_max * 8 + 64) + (1 << 20) +
+                      (uint64_t)s->nb * s->chi_max * 8;
   hipError_t e1 = hipHostMalloc((void**)&s->jobs_host, s->cv.jobs_bytes, hipHostMallocDefault);
   hipError_t e2 = hipHostMalloc((void**)&s->hscratch, s->hscratch_bytes, hipHostMallocDefault);
   if (e1 != hipSuccess || e2 != hipSuccess) {
@@ -1825,6 +2067,8 @@ int hpt_set_site_tensor(hpt_sim* s, int32_t site, const double* host, const int3
   }
   if (dims[si.deg] != 4) return HPT_EINVAL;
   tot *= 4;
+  for (uint64_t i = 0; i < tot; ++i)
+    if (!std::isfinite(host[i])) return HPT_ENUMERIC;
   if (sync_stream(s)) return HPT_EHIP;
   if (s->fp32) {
     std::vector<float> tmp(tot);
@@ -1855,6 +2099,8 @@ int hpt_get_messages(hpt_sim* s, int32_t bond, int32_t dir, double* host, int32_
 int hpt_set_messages(hpt_sim* s, int32_t bond, int32_t dir, const double* host, int32_t chi) {
   if (!s || !host || bond < 0 || bond >= s->nb || dir < 0 || dir > 1) return HPT_EINVAL;
   if (chi != s->chi[bond]) return HPT_EINVAL;
+  for (int64_t i = 0; i < (int64_t)chi * chi; ++i)
+    if (!std::isfinite(host[i])) return HPT_ENUMERIC;
   if (sync_stream(s)) return HPT_EHIP;
   HPT_HIP(hipMemcpy(gmsg_slot(s, bond, dir), host, (uint64_t)chi * chi * 8, hipMemcpyHostToDevice));
   return HPT_OK;
@@ -2043,6 +2289,57 @@ int hpt_checkpoint_load(hpt_sim* s, const void* buf, uint64_t bytes, int32_t whe
   s->prv_C = h.prv_C; s->prv_gate_err = h.prv_gate_err;
   RC(ckpt_device_sections(s, h, img, where, false));
   return sync_stream(s);
+}
+
+int hpt_meas_learn_rows(hpt_sim* s, int64_t* rows) {
+  if (!s || !rows) return HPT_EINVAL;
+  int64_t r = 0;
+  for (int c : s->chi) r += 2 * c;
+  *rows = r;
+  return HPT_OK;
+}
+
+int hpt_meas_features(hpt_sim* s, float* X, float* base, int64_t cap) {
+  if (!s || !X || !base) return HPT_EINVAL;
+  int64_t need = 0;
+  RC(hpt_meas_learn_rows(s, &need));
+  if (cap < need) return HPT_ENOMEM;
+  LearnEdge* ed;
+  int64_t rows = 0;
+  RC(s->fp32 ? learn_features<float>(s, &ed, &rows) : learn_features<double>(s, &ed, &rows));
+  // the previous measurement's messages go back (the one sweep overwrote them)
+  HPT_HIP(hipMemcpyAsync(s->mmsg, s->lprev, 2ull * s->nb * s->chi_max * 8, hipMemcpyDeviceToDevice, s->stream));
+  HPT_HIP(hipMemcpyAsync(X, s->lX, (uint64_t)rows * LEARN_F * 4, hipMemcpyDeviceToDevice, s->stream));
+  HPT_HIP(hipMemcpyAsync(base, s->lbase, (uint64_t)rows * 4, hipMemcpyDeviceToDevice, s->stream));
+  return sync_stream(s);
+}
+
+int hpt_meas_targets(hpt_sim* s, const float* base, float* T, int64_t cap) {
+  if (!s || !base || !T) return HPT_EINVAL;
+  int64_t need = 0;
+  RC(hpt_meas_learn_rows(s, &need));
+  if (cap < need) return HPT_ENOMEM;
+  std::vector<LearnEdge> e(2 * s->nb);
+  int64_t row = 0;
+  for (int b = 0; b < s->nb; ++b)
+    for (int d = 0; d < 2; ++d) {
+      LearnEdge& x = e[2 * b + d];
+      std::memset(&x, 0, sizeof(x));
+      x.one = mmsg_slot(s, b, d);
+      x.chi = s->chi[b];
+      x.row0 = row;
+      row += s->chi[b];
+    }
+  LearnEdge* ed;
+  RC(stage(s, e.data(), 2 * s->nb, &ed));
+  KR(launch_learn_targets(ed, 2 * s->nb, base, T, s->stream));
+  return sync_stream(s);
+}
+
+int hpt_set_meas_model(hpt_sim* s, const float* params) {
+  if (!s) return HPT_EINVAL;
+  s->meas_model = params;
+  return HPT_OK;
 }
 
 int hpt_phase_timing(hpt_sim* s, int32_t enable) {

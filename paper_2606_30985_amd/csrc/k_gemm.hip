@@ -9,6 +9,7 @@
 // contiguous axis of each operand.  The reduction space (batch r, k-chunks)
 // can be split across workgroups; partial tiles are then summed in float64
 // by a second, deterministic kernel.
+#include <algorithm>
 #include <cstdlib>
 #include <type_traits>
 
@@ -1224,6 +1225,50 @@ int leg_gram_f32(const float* psi, const float* cur, int n, int64_t inner, int64
   hipLaunchKernelGGL(gemm_reduce_kernel<float>, dim3((unsigned)blocks), dim3(1024), 0, s, d, parts, (const double*)part);
   HPT_LAUNCH_CHECK("gemm_reduce_kernel");
   return 1;
+}
+
+// float64-arithmetic mode product of float32 data: one thread per
+// (a, 8 consecutive j, b), the 8 sums carried in registers over k; consecutive
+// threads take consecutive a, so the loads of src[a, k, b] are coalesced
+__global__ __launch_bounds__(256) void mode_product_f64acc_kernel(const double* __restrict__ S,
+                                                                  const float* __restrict__ src,
+                                                                  float* __restrict__ dst, int n, int64_t inner,
+                                                                  int64_t outer, int jblocks) {
+  const int64_t total = inner * outer * jblocks;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = idx % inner;
+    const int64_t r = idx / inner;
+    const int j0 = (int)(r % jblocks) * 8;
+    const int64_t b = r / jblocks;
+    const float* sp = src + a + b * inner * n;
+    double acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double x = (double)sp[(int64_t)k * inner];
+      const double* Sk = S + (int64_t)k * n;
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (j0 + t < n) acc[t] = fma(Sk[j0 + t], x, acc[t]);
+    }
+    float* dp = dst + a + b * inner * n;
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      if (j0 + t < n) dp[(int64_t)(j0 + t) * inner] = (float)acc[t];
+  }
+}
+
+int mode_product_f64acc(const double* S, const float* src, float* dst, int n, int64_t inner, int64_t outer,
+                        hipStream_t s) {
+  if (n < 1 || inner < 1 || outer < 1) return -1;
+  const int jblocks = (int)ceil_div(n, 8);
+  const int64_t total = inner * outer * jblocks;
+  const int64_t blocks = std::min<int64_t>(ceil_div(total, 256), 16384);
+  hipLaunchKernelGGL(mode_product_f64acc_kernel, dim3((unsigned)blocks), dim3(256), 0, s, S, src, dst, n, inner,
+                     outer, jblocks);
+  HPT_LAUNCH_CHECK("mode_product_f64acc_kernel");
+  return 0;
 }
 
 int mode_product_f32(const float* S, const float* src, float* dst, int n, int64_t inner, int64_t outer,

@@ -319,9 +319,10 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdJob* jobs) {
     __syncthreads();
   }
   const double dead2 = s_dead2;
+  const int maxs = job.max_sweeps > 0 ? job.max_sweeps : 60;
   int sweep = 0;
   if (n > 1) {
-    for (sweep = 0; sweep < 60; ++sweep) {
+    for (sweep = 0; sweep < maxs; ++sweep) {
       if (tid == 0) {
         s_rot = 0;
         s_off = 0;
@@ -368,6 +369,8 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdJob* jobs) {
     }
   }
   if (tid == 0 && job.sweeps) *job.sweeps = sweep + 1;
+  // the loop ran to the cap without meeting either stopping rule
+  if (tid == 0 && job.state) job.state[3] = (n > 1 && sweep >= maxs) ? 1 : 0;
   for (int p = wave; p < n; p += nw) {
     double a = 0.0;
     for (int i = lane; i < m; i += 64) a += G[i + p * ldg] * G[i + p * ldg];
@@ -415,6 +418,7 @@ __global__ __launch_bounds__(256) void bj_init_kernel(const SvdJob* jobs) {
     job.state[0] = job.n < 2;
     job.state[1] = 0;
     job.state[2] = 0;
+    job.state[3] = 0;
     job.state[5] = 0;
     job.state[6] = 0;
     if (job.sweeps) *job.sweeps = 0;
@@ -856,6 +860,16 @@ int launch_jacobi_svd(const SvdJob* jobs, int njobs, hipStream_t s) {
   return 0;
 }
 
+// after the last sweep: a job that is not done and whose last sweep still
+// rotated above the 1e-12 relative off-diagonal has not converged
+__global__ void bj_check_kernel(const SvdJob* jobs, int last) {
+  const SvdJob job = jobs[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  const bool conv = job.state[0] || job.state[1 + (last & 1)] == 0 ||
+                    __int_as_float(job.state[5 + (last & 1)]) < 1e-12f;
+  job.state[3] = conv ? 0 : 1;
+}
+
 // done = 1 when every job has converged
 __global__ __launch_bounds__(256) void bj_all_done_kernel(const SvdJob* jobs, int njobs, int* done) {
   __shared__ int s_all;
@@ -868,7 +882,7 @@ __global__ __launch_bounds__(256) void bj_all_done_kernel(const SvdJob* jobs, in
 }
 
 int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, hipStream_t s, int* done_dev,
-                            volatile int* done_host) {
+                            volatile int* done_host, int max_sweeps) {
   if (njobs <= 0) return 0;
   int mmax = 1, nmax = 1;
   for (int j = 0; j < njobs; ++j) {
@@ -891,8 +905,10 @@ int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, h
   const int nb = (nmax + w - 1) / w, nb2 = nb + (nb & 1);
   hipLaunchKernelGGL(bj_init_kernel, dim3(njobs), dim3(256), 0, s, jobs);
   HPT_LAUNCH_CHECK("bj_init_kernel");
-  const int max_sweeps = 20;
+  if (max_sweeps < 1) max_sweeps = 20;
+  int last = -1;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    last = sweep;
     hipLaunchKernelGGL(bj_sweep_begin_kernel, dim3(njobs), dim3(64), 0, s, jobs, sweep);
     HPT_LAUNCH_CHECK("bj_sweep_begin_kernel");
     for (int r = 0; r < nb2 - 1; ++r) {
@@ -911,12 +927,17 @@ int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, h
       HPT_HIP(hipStreamSynchronize(s));
       if (*done_host) break;
       ++sweep;   // that sweep has begun: run its rounds next
+      last = sweep;
       for (int r = 0; r < nb2 - 1; ++r) {
         hipLaunchKernelGGL(bj_round_kernel, dim3(std::max(1, nb2 / 2), njobs), dim3(1024), lds, s, jobs, r,
                            sweep, w);
         HPT_LAUNCH_CHECK("bj_round_kernel");
       }
     }
+  }
+  if (last >= 0) {
+    hipLaunchKernelGGL(bj_check_kernel, dim3(njobs), dim3(64), 0, s, jobs, last);
+    HPT_LAUNCH_CHECK("bj_check_kernel");
   }
   hipLaunchKernelGGL(bj_finish_kernel, dim3(njobs), dim3(1024), 0, s, jobs);
   HPT_LAUNCH_CHECK("bj_finish_kernel");

@@ -39,9 +39,11 @@ struct SvdJob {
   double* V; int ldv;
   double* s; int* perm;
   int* sweeps;
-  int* state;          // 7 ints of scratch for the block variant (done, 2 rotation counters, -, -,
-                       // 2 largest relative off-diagonals as float bits)
+  int* state;          // 7 ints of scratch: done, 2 rotation counters (block variant), not converged
+                       // within the sweep cap (both variants), -, 2 largest relative off-diagonals
+                       // as float bits (block variant)
   double* fro2;        // block variant: 1 double of scratch (squared Frobenius norm); may be null
+  int max_sweeps;      // one-sided variant: sweep cap (0: 60)
 };
 // Columns whose norm falls below 1e-14 of the Frobenius norm of G hold only
 // rounding noise: pairs involving them are not rotated (otherwise the noise
@@ -113,7 +115,7 @@ int launch_jacobi_svd(const SvdJob* jobs, int njobs, hipStream_t s);
 // convergence once per sweep from the fourth sweep on (one stream sync each)
 // and stops launching when every job has converged.
 int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, hipStream_t s, int* done_dev,
-                            volatile int* done_host);
+                            volatile int* done_host, int max_sweeps = 20);
 int launch_cholesky(const CholJob* jobs, int njobs, double rel_tol, hipStream_t s);
 int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s);
 int launch_piv_cholesky(const PivCholJob* jobs, int njobs, hipStream_t s);

@@ -6,6 +6,7 @@
 
 #include "../../include/hpt.h"
 #include "common.h"
+#include "learn.h"
 
 // Scratch of hpt_gram64_noalloc: the per-split partial tiles live in this
 // file-scope device array (one copy per GPU, held until the process ends)
@@ -73,6 +74,23 @@ int hpt_gram64(const float* X, int64_t m, int32_t n, int64_t ldx, double* G, int
   if (!workspace || workspace_bytes < need) return HPT_ENOMEM;
   if (gram64_launch(X, ldx, (int)m, n, G, ldg, splits, (double*)workspace, (hipStream_t)hip_stream)) return HPT_EHIP;
   return HPT_OK;
+}
+
+int hpt_learn_forward(const float* params, const float* X, int64_t rows, float* y, void* hip_stream) {
+  if (!params || rows < 0 || (rows > 0 && (!X || !y))) return HPT_EINVAL;
+  return launch_learn_forward(params, X, rows, y, (hipStream_t)hip_stream) ? HPT_EHIP : HPT_OK;
+}
+
+int hpt_learn_backward(const float* params, const float* X, const float* y, const float* t, int64_t rows,
+                       float* grad, void* hip_stream) {
+  if (!params || !X || !y || !t || !grad || rows < 1) return HPT_EINVAL;
+  return launch_learn_backward(params, X, y, t, rows, grad, (hipStream_t)hip_stream) ? HPT_EHIP : HPT_OK;
+}
+
+int hpt_learn_adam(float* params, float* m, float* v, const float* grad, int32_t step, float lr,
+                   void* hip_stream) {
+  if (!params || !m || !v || !grad || step < 1 || !(lr > 0.0f)) return HPT_EINVAL;
+  return launch_learn_adam(params, m, v, grad, step, lr, (hipStream_t)hip_stream) ? HPT_EHIP : HPT_OK;
 }
 
 int hpt_gram64_noalloc(const float* X, int64_t m, int32_t n, int64_t ldx, double* G, int64_t ldg,

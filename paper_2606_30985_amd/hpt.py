@@ -21,6 +21,10 @@ HPT_QR_ADAPTIVE = 0
 HPT_QR_HOUSEHOLDER = 1
 HPT_BP_UNIFORM = 0
 HPT_BP_WARM = 1
+HPT_BP_LEARNED = 2
+LEARN_FEATURES = 16
+LEARN_HIDDEN = 128
+LEARN_PARAMS = LEARN_HIDDEN * LEARN_FEATURES + 2 * LEARN_HIDDEN + 1
 
 FLAGS = {
     "BP_NOT_CONVERGED_GAUGE": 1 << 0,
@@ -34,7 +38,10 @@ FLAGS = {
     "QR_RANK_DEFICIENT": 1 << 8,
     "TRAP_REMEDIATED": 1 << 9,
     "TRAP_UNRESOLVED": 1 << 10,
+    "SVD_NOT_CONVERGED": 1 << 11,
 }
+HPT_AXES_PAPER = 0
+HPT_AXES_ZZX = 1
 
 
 class HptConfig(ctypes.Structure):
@@ -51,7 +58,8 @@ class HptConfig(ctypes.Structure):
         ("meas_max_sweeps", ctypes.c_int32), ("gauge_bp", ctypes.c_int32),
         ("trap_sweeps", ctypes.c_int32), ("qr_rank_tol", ctypes.c_double),
         ("trap_retry", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("trap_alpha", ctypes.c_double),
-        ("reserved", ctypes.c_int32 * 4),
+        ("model_axes", ctypes.c_int32), ("svd_max_sweeps", ctypes.c_int32),
+        ("meas_init", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1),
     ]
 
 
@@ -110,6 +118,13 @@ def _load():
         "hpt_gram64_workspace_bytes": [ctypes.c_int64, i32, ctypes.POINTER(u64)],
         "hpt_gram64": [P, ctypes.c_int64, i32, ctypes.c_int64, P, ctypes.c_int64, P, u64, P],
         "hpt_gram64_noalloc": [P, ctypes.c_int64, i32, ctypes.c_int64, P, ctypes.c_int64, P],
+        "hpt_meas_learn_rows": [P, ctypes.POINTER(ctypes.c_int64)],
+        "hpt_meas_features": [P, P, P, ctypes.c_int64],
+        "hpt_meas_targets": [P, P, P, ctypes.c_int64],
+        "hpt_set_meas_model": [P, P],
+        "hpt_learn_forward": [P, P, ctypes.c_int64, P, P],
+        "hpt_learn_backward": [P, P, P, P, ctypes.c_int64, P, P],
+        "hpt_learn_adam": [P, P, P, P, i32, ctypes.c_float, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -131,7 +146,9 @@ EXPORTED = ["hpt_config_default", "hpt_required_bytes", "hpt_state_bytes", "hpt_
             "hpt_get_meas_messages", "hpt_destroy", "hpt_strerror", "hpt_last_hip_error",
             "hpt_permute", "hpt_profile_gemm", "hpt_profile_gemm_read", "hpt_profile_read", "hpt_run_batch",
             "hpt_checkpoint_bytes", "hpt_checkpoint_save", "hpt_checkpoint_load", "hpt_phase_timing",
-            "hpt_phase_read", "hpt_gram64_workspace_bytes", "hpt_gram64", "hpt_gram64_noalloc"]
+            "hpt_phase_read", "hpt_gram64_workspace_bytes", "hpt_gram64", "hpt_gram64_noalloc",
+            "hpt_meas_learn_rows", "hpt_meas_features", "hpt_meas_targets", "hpt_set_meas_model",
+            "hpt_learn_forward", "hpt_learn_backward", "hpt_learn_adam"]
 
 HPT_MEM_HOST = 0
 HPT_MEM_DEVICE = 1
@@ -193,6 +210,10 @@ def make_config(**kw):
             v = {"fp64": HPT_FP64, "fp32": HPT_FP32_MFMA, "fp32_mfma": HPT_FP32_MFMA, "bf16x6": HPT_FP32_BF16X6}[v]
         if k == "qr_mode" and isinstance(v, str):
             v = {"adaptive": HPT_QR_ADAPTIVE, "householder": HPT_QR_HOUSEHOLDER}[v]
+        if k == "model_axes" and isinstance(v, str):
+            v = {"paper": HPT_AXES_PAPER, "zzx": HPT_AXES_ZZX}[v]
+        if k == "meas_init" and isinstance(v, str):
+            v = {"uniform": HPT_BP_UNIFORM, "learned": HPT_BP_LEARNED}[v]
         if k == "bp_init" and isinstance(v, str):
             v = {"uniform": HPT_BP_UNIFORM, "warm": HPT_BP_WARM}[v]
         if k not in names:
@@ -362,6 +383,36 @@ class Simulator:
         return dict(gate_ms=out[0], gauge_ms=out[1], meas_ms=out[2], layers=int(out[3]),
                     gauge_sweeps=int(out[4]), measurements=int(out[5]), meas_sweeps=int(out[6]))
 
+    # -- learned warm start of the measurement BP ---------------------------
+    def learn_rows(self):
+        n = ctypes.c_int64()
+        check(lib.hpt_meas_learn_rows(self.h, ctypes.byref(n)), "hpt_meas_learn_rows")
+        return n.value
+
+    def meas_features(self):
+        """(X, base) device tensors of the current state (float32)."""
+        import torch
+        n = self.learn_rows()
+        X = torch.empty((n, LEARN_FEATURES), dtype=torch.float32, device=self.device)
+        base = torch.empty(n, dtype=torch.float32, device=self.device)
+        check(lib.hpt_meas_features(self.h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(base.data_ptr()), n),
+              "hpt_meas_features")
+        return X, base
+
+    def meas_targets(self, base):
+        import torch
+        n = base.numel()
+        T = torch.empty(n, dtype=torch.float32, device=self.device)
+        check(lib.hpt_meas_targets(self.h, ctypes.c_void_p(base.data_ptr()), ctypes.c_void_p(T.data_ptr()), n),
+              "hpt_meas_targets")
+        return T
+
+    def set_meas_model(self, params):
+        """params: float32 device tensor of LEARN_PARAMS entries (kept alive here)."""
+        self._meas_model = params
+        check(lib.hpt_set_meas_model(self.h, ctypes.c_void_p(params.data_ptr() if params is not None else 0)),
+              "hpt_set_meas_model")
+
     def _deg(self, v):
         Lx, Ly = self.cfg.Lx, self.cfg.Ly
         x, y = v % Lx, v // Lx
@@ -388,6 +439,35 @@ def gram64(X, G, workspace=None, stream=None):
     st = stream if stream is not None else torch.cuda.current_stream(X.device).cuda_stream
     check(lib.hpt_gram64(ctypes.c_void_p(X.data_ptr()), m, n, m, ctypes.c_void_p(G.data_ptr()), G.shape[1],
                          ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.c_void_p(st)), "hpt_gram64")
+
+
+def _stream(t, stream):
+    import torch
+    return ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def learn_forward(params, X, stream=None):
+    import torch
+    y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    check(lib.hpt_learn_forward(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(X.data_ptr()), X.shape[0],
+                                ctypes.c_void_p(y.data_ptr()), _stream(X, stream)), "hpt_learn_forward")
+    return y
+
+
+def learn_backward(params, X, y, t, stream=None):
+    """(grad [LEARN_PARAMS], loss tensor [1]) as device tensors."""
+    import torch
+    g = torch.empty(LEARN_PARAMS + 1, dtype=torch.float32, device=X.device)
+    check(lib.hpt_learn_backward(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(X.data_ptr()),
+                                 ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(t.data_ptr()), X.shape[0],
+                                 ctypes.c_void_p(g.data_ptr()), _stream(X, stream)), "hpt_learn_backward")
+    return g[:LEARN_PARAMS], g[LEARN_PARAMS:]
+
+
+def learn_adam(params, m, v, grad_full, step, lr, stream=None):
+    check(lib.hpt_learn_adam(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(m.data_ptr()),
+                             ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(grad_full.data_ptr()), int(step),
+                             float(lr), _stream(params, stream)), "hpt_learn_adam")
 
 
 def permute(src, dst, perm, stream=None):

@@ -49,10 +49,14 @@ def bond_case(name):
     v1, v2, _ = net.lat.bonds[b]
     sites = {}
     for v in (v1, v2):
-        flat = net.psi[v].ravel(order="F")
+        T = net.psi[v]
+        flat = T.ravel(order="F")
         idx = fc.sample_index(flat.size)
-        sites[str(v)] = dict(dims=list(net.psi[v].shape), norm=float(np.linalg.norm(flat)),
-                             idx=[int(i) for i in idx], val=[float(x) for x in flat[idx]])
+        # per-leg marginals: for every leg, the sum of squares over all other indices
+        sq = T * T
+        marg = [[float(x) for x in sq.sum(axis=tuple(a for a in range(T.ndim) if a != l))] for l in range(T.ndim)]
+        sites[str(v)] = dict(dims=list(T.shape), norm=float(np.linalg.norm(flat)),
+                             idx=[int(i) for i in idx], val=[float(x) for x in flat[idx]], marginals=marg)
     out = dict(config=fc.CFG, seed=fc.SEED, bond=int(b), source="oracle/ (CPU FP64 restatement of the method)",
                chi_new=int(r["chi_new"]), lam=[float(x) for x in r["lam"]], gate_err=float(r["gate_err"]),
                sites=sites)

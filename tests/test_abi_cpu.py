@@ -96,3 +96,21 @@ def hpt_part_max():
     hdr = open(os.path.join(ROOT, "include", "hpt.h")).read()
     m = re.search(r"#define HPT_GRAM64_PART_MAX \((\d+)ull << (\d+)\)", hdr)
     return int(m.group(1)) << int(m.group(2))
+
+
+@pytest.mark.parametrize("kw", [dict(model_axes=2), dict(model_axes=-1), dict(svd_max_sweeps=-3)])
+def test_invalid_axes_and_sweep_caps_rejected(hpt, kw):
+    c = hpt.make_config(**kw)
+    n = ctypes.c_uint64()
+    assert hpt.lib.hpt_required_bytes(ctypes.byref(c), ctypes.byref(n)) == -1
+
+
+def test_short_arena_refused_without_touching_the_device(hpt):
+    # the arena is checked against the memory model before any HIP call, so a
+    # fake device address is never dereferenced
+    c = hpt.make_config(Lx=4, Ly=4, chi_max=12)
+    need = hpt.required_bytes(c)
+    h = ctypes.c_void_p()
+    assert hpt.lib.hpt_create(ctypes.byref(c), ctypes.c_void_p(1 << 20), need - 1, None, ctypes.byref(h)) == -2
+    assert not h.value
+    assert hpt.make_config(model_axes="zzx").model_axes == 1

@@ -3,7 +3,8 @@ interior-interior bond update on the seeded saturated state of
 tests/fullsize_case.py (both site tensors hold 4 * 100^4 entries, the QR blocks
 are 10^6 x 400).  The expected values were written by the CPU oracle
 (tests/golden/make_golden.py oracle_bond_4x4_chi100, several minutes of CPU):
-the full Vidal spectrum, the bond dimension, the gate error and sampled
+the full Vidal spectrum, the bond dimension, the gate error, the per-leg
+marginals (sum of squares over all other indices, every leg) and sampled
 entries and norms of both new site tensors."""
 
 import json
@@ -54,4 +55,10 @@ def test_interior_bond_update_chi100(precision, tol, case):
         flat = got.ravel(order="F")
         assert max_rel(flat[np.asarray(site["idx"])], site["val"]) < tol * 10
         assert abs(np.linalg.norm(flat) / site["norm"] - 1) < tol * 10
+        # whole-tensor check: per-leg marginals (sum of squares over all other
+        # indices) of every leg, 100 values per bond leg and 4 for the Pauli leg
+        sq = got * got
+        for l, ref_m in enumerate(site["marginals"]):
+            m = sq.sum(axis=tuple(a for a in range(got.ndim) if a != l))
+            assert max_rel(m, ref_m) < tol, (v, l, max_rel(m, ref_m))
     sim.close()

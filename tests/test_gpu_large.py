@@ -64,10 +64,9 @@ def test_10x10_chi100_fp32_form_against_fp64():
         assert cmp, "no layer with both measurement BPs converged"
         early = [r for r in cmp if r["t"] <= 1.0 + 1e-12]
         if name == "fp32":
-            # layers up to t = 1.0 (chi below chi_max on most bonds): float32
-            # storage and the gauge BP's 1e-5 tolerance leave |dC| at the 1e-6
-            # level
-            assert max(r["dC"] for r in early) <= 5e-6, name
+            # the target of the float32 form, on every layer: |dC| <= 1e-6
+            # (measured 8.8e-7 at most, 2.3e-7 on layers 29-30)
+            assert max(r["dC"] for r in cmp) <= 1e-6, name
         else:
             # the split-bf16 products have float32-level error per product,
             # yet on this workload C(t) drifts one-signed from the FP64 run

@@ -72,17 +72,18 @@ def test_config0_fp32_form(precision):
     worst = max(abs(got[k]["C"] - rec["C"]) for k, rec in enumerate(g["records"]))
     print(precision, "form worst |dC| on 3x3 chi 8:", worst, "per layer:",
           " ".join(f"{abs(got[k]['C'] - rec['C']):.1e}" for k, rec in enumerate(g["records"])))
-    assert worst <= 2e-6
+    # target of the float32 form: |dC| <= 1e-6 (measured 3.8e-7 / 6.8e-7)
+    assert worst <= 1e-6
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
 def test_config1_chi20_fp32_form(precision):
     # the float32 form on 4x4 chi 20: |dC| against the float64 oracle, first
-    # 30 layers.  Up to t = 0.9 (layer 18) the difference stays at the level
-    # set by the float32 gauge BP (converged to 1e-6, its float32 floor, so
-    # the gauge and through it the Bethe estimate differ by ~1e-6); later
-    # every layer truncates (gate error ~1e-3), and rounding-level changes of
-    # the spectrum at the cut move C(t) by up to about 1e-5
+    # 30 layers.  Up to t = 0.9 (layer 18) the difference stays below 1e-6
+    # (measured 4.6e-7; 1.4e-6 with the split-bf16 products); later every
+    # layer truncates hard at chi 20 (gate error ~1e-3) with the gauge BP
+    # converged only to its float32 floor (1e-6), so the kept subspace and
+    # through it C(t) move by up to about 1e-5
     hpt = load_hpt()
     g = _golden("oracle_4x4_chi20")
     cfg = dict(g["config"])
@@ -90,8 +91,8 @@ def test_config1_chi20_fp32_form(precision):
     got = _traj(hpt, cfg, 30, precision=precision)
     d = [abs(got[k]["C"] - g["records"][k]["C"]) for k in range(31)]
     print(precision, "form |dC| on 4x4 chi 20 per layer:", " ".join(f"{x:.1e}" for x in d))
-    assert max(d[:19]) <= 4e-6
-    assert max(d) <= 5e-5
+    assert max(d[:19]) <= (1e-6 if precision == "fp32" else 2e-6)
+    assert max(d) <= 3e-5
 
 
 def test_config1_chi20_trap_retry():
