@@ -64,9 +64,9 @@ def parse():
     ap.add_argument("--trace", default="", help="append per-step records (JSON lines) to this file")
     ap.add_argument("--profile-all", action="store_true",
                     help="kernel event profile over every layer (warm-up included), for counter comparisons")
-    ap.add_argument("--workload", default="large", choices=["large", "batched", "learned"],
+    ap.add_argument("--workload", default="large", choices=["large", "batched", "learned", "permute"],
                     help="large: the 10x10 chi=100 run (default); batched: the independent-runs set; "
-                         "learned: the learned warm start of the measurement BP")
+                         "learned: the learned warm start of the measurement BP; permute: device permutations")
     ap.add_argument("--learn-steps", type=int, default=3000)
     ap.add_argument("--batch-runs", type=int, default=64)
     ap.add_argument("--batch-chi", type=int, default=40)
@@ -240,6 +240,71 @@ def batched(args):
     print(json.dumps(out), flush=True)
 
 
+def permutes(args):
+    """Microbenchmark of the gate update's device permutations: for every
+    site degree (4 interior, 3 edge, 2 corner) and every cut leg that is not
+    already last, the forward move [.., cut, .., P] -> [.., .., cut, P] and its
+    inverse, at chi in {20, 40, 60, 100} and one uneven boundary shape, float32
+    and float64 (seeded random data).  Each case: one untimed call, then the
+    mean of 5 calls between HIP events on the launch stream; GB/s = bytes read
+    + bytes written per call / time.  Every result is checked bit for bit
+    against torch's permute."""
+    import numpy as np
+    import torch
+    from paper_2606_30985_amd import hpt
+    rows = []
+    shapes = []
+    for chi in (20, 40, 60, 100):
+        for deg in (4, 3, 2):
+            shapes.append((f"deg{deg} chi{chi}", [chi] * deg))
+    shapes.append(("deg4 uneven", [100, 37, 100, 61]))
+    g = torch.Generator(device="cuda").manual_seed(0)
+    for name, legs in shapes:
+        deg = len(legs)
+        for dt in (torch.float32, torch.float64):
+            n = int(np.prod(legs)) * 4
+            src = torch.randn(n, generator=g, dtype=torch.float32, device="cuda").to(dt)
+            dst = torch.empty_like(src)
+            for cut in range(deg - 1):
+                dims = legs + [4]
+                fwd = [l for l in range(deg) if l != cut] + [cut, deg]
+                pdims = [dims[k] for k in fwd]
+                inv = [fwd.index(k) for k in range(deg + 1)]
+                for direction, (d_in, perm) in (("fwd", (dims, fwd)), ("inv", (pdims, inv))):
+                    x = src.view(*d_in[::-1]).permute(*range(deg, -1, -1))
+                    hpt.permute(x, dst, perm)
+                    ref = x.permute(*perm).permute(*range(deg, -1, -1)).contiguous().view(-1)
+                    if not torch.equal(dst, ref):
+                        raise SystemExit(f"permute mismatch {name} cut {cut} {direction} {dt}")
+                    st = torch.cuda.current_stream()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(st)
+                    for _ in range(5):
+                        hpt.permute(x, dst, perm)
+                    e1.record(st)
+                    torch.cuda.synchronize()
+                    ms = e0.elapsed_time(e1) / 5
+                    nbytes = 2 * n * src.element_size()
+                    rows.append({"shape": name, "dims": d_in, "cut": cut, "dir": direction,
+                                 "dtype": "f32" if dt == torch.float32 else "f64", "bytes": nbytes,
+                                 "ms": ms, "GBps": nbytes / ms / 1e6})
+                    print(f"# {name} {rows[-1]['dtype']} cut {cut} {direction}: {ms * 1e3:.1f} us "
+                          f"{rows[-1]['GBps']:.0f} GB/s", file=sys.stderr, flush=True)
+            del src, dst, ref
+            torch.cuda.empty_cache()
+    big = [r for r in rows if r["bytes"] >= 256e6]
+    gb = sorted(r["GBps"] for r in big)
+    out = {"metric": "device permutation bandwidth of the gate update (cut leg next to the Pauli leg and back)",
+           "value": gb[len(gb) // 2], "unit": "GB/s (median over moves of >= 256 MB)", "n_gpus": 1,
+           "steps": 5, "warmup": 1, "ms_per_step": sum(r["ms"] for r in rows) / len(rows),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32/f64 (bit copies)",
+           "data": "synthetic (seeded random tensors)",
+           "config": {"workload": "every degree, cut leg and direction at chi 20/40/60/100 and one uneven shape",
+                      "min_GBps_over_256MB": gb[0], "frac_of_8TBps_median": gb[len(gb) // 2] / 8000.0,
+                      "cases": rows}}
+    print(json.dumps(out), flush=True)
+
+
 def learned(args):
     """The learned warm start of the measurement BP: training data from runs
     of the method (4x4 at chi 20/40 and batched-form lattices 3x3..6x6 at chi
@@ -388,6 +453,37 @@ def run_layer(sim, torch, tag, trace=None):
     return rec
 
 
+def site_bonds(L):
+    """Bond ids of every site of an L x L lattice (legs U, D, L, R where present)."""
+    nh = (L - 1) * L
+    out = []
+    for y in range(L):
+        for x in range(L):
+            legs = []
+            if y > 0:
+                legs.append(nh + (y - 1) * L + x)
+            if y < L - 1:
+                legs.append(nh + y * L + x)
+            if x > 0:
+                legs.append(y * (L - 1) + x - 1)
+            if x < L - 1:
+                legs.append(y * (L - 1) + x)
+            out.append(legs)
+    return out
+
+
+def meas_sweep_bytes(chis, L, elem):
+    """Algorithmic bytes of one measurement sweep: every pinned slice
+    (prod of the site's bond dimensions) read once."""
+    tot = 0
+    for legs in site_bonds(L):
+        n = 1
+        for b in legs:
+            n *= chis[b]
+        tot += n * elem
+    return tot
+
+
 def chi_stats(sim):
     chis = [sim.chi(b) for b in range(sim.n_bonds)]
     return chis, {"min": min(chis), "mean": sum(chis) / len(chis), "max": max(chis)}
@@ -403,6 +499,8 @@ def main():
         return batched(args)
     if args.workload == "learned":
         return learned(args)
+    if args.workload == "permute":
+        return permutes(args)
     import torch
     from paper_2606_30985_amd import hpt
 
@@ -430,6 +528,7 @@ def main():
         r = run_layer(sim, torch, f"{args.precision} ramp", trace)
         traj[r["step"]] = r
     chis, cst = chi_stats(sim)
+    msb = meas_sweep_bytes(chis, L, 8 if args.precision == "fp64" else 4)
     cb = centre_bonds(L)
     if any(chis[b] != chi for b in cb) and not args.allow_unsaturated:
         print(f"# centre bonds {[chis[b] for b in cb]} are not at chi_max={chi} after layer {ramp}",
@@ -566,6 +665,8 @@ def main():
                    "meas_sweeps_per_layer": phase["meas_sweeps"] / max(phase["measurements"], 1),
                    "gauge_sweep_ms": phase["gauge_ms"] / max(phase["gauge_sweeps"], 1),
                    "meas_sweep_ms": phase["meas_ms"] / max(phase["meas_sweeps"], 1),
+                   "meas_sweep_bytes_at_snapshot": msb,
+                   "meas_phase_GBps": msb * phase["meas_sweeps"] / max(phase["meas_ms"] * 1e6, 1e-30),
                    "bond_classes": per_class,
                    "C": {str(k): traj[k]["C"] for k in sorted(traj)},
                    "fp64_form": fp64,

@@ -303,7 +303,31 @@ __global__ __launch_bounds__(256) void last_leg_kernel(const LastLegJob* jobs, i
     }
     xr[q] = v;
   }
-  for (int e = 0; e < nL; ++e) {
+  // columns in groups of four: the 16 loads of a group are issued together
+  // (more bytes in flight per wave), then folded and reduced column by column
+  int e = 0;
+  for (; e + 4 <= nL; e += 4) {
+    double t[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const T* col = Tp + rows * (e + c);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t[c][q] = rr[q] < rows ? (double)col[rr[q]] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double me = job.mL[e + c];
+      double sacc = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        pacc[q] += t[c][q] * me;
+        sacc += t[c][q] * xr[q];
+      }
+      sacc = wave_sum(sacc);
+      if (lane == 0) wp[wave][e + c] = sacc;
+    }
+  }
+  for (; e < nL; ++e) {
     const double me = job.mL[e];
     const T* col = Tp + rows * e;
     double sacc = 0.0;

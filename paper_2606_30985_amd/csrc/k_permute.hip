@@ -4,11 +4,14 @@
 //
 // The gate update only ever swaps two groups of axes between a fast group
 // and the Pauli axis: [A, B, C, P] -> [A, C, B, P] (A = legs before the cut,
-// B = the cut leg, C = legs after it).  When A is large every element map is
-// coalesced along A; when A == 1 the (B, C) plane is transposed through a
-// 64 x 64 LDS tile so that reads run along B and writes along C.  A generic
+// B = the cut leg, C = legs after it).  When A is large the move is a gather
+// of whole A-element rows (16-byte vectors); when A is small the (B, C) plane
+// is transposed through a 64 x 64 LDS tile so that reads run along B and
+// writes along C.  A generic
 // rank <= 8 kernel (one thread per output element) serves everything else.
 // All paths are plain copies: bit-exact.
+#include <algorithm>
+
 #include "common.h"
 
 namespace hpt {
@@ -36,20 +39,50 @@ __global__ void permute_generic_kernel(const E* __restrict__ in, E* __restrict__
   }
 }
 
-// out[a, c, b, p] = in[a, b, c, p], A large: one thread per output element
-template <typename E>
-__global__ void swap_mid_elem_kernel(const E* __restrict__ in, E* __restrict__ out, int64_t A,
-                                     int64_t B, int64_t C, int64_t total) {
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t a = idx % A;
-    int64_t rest = idx / A;
-    const int64_t c = rest % C;
-    rest /= C;
-    const int64_t b = rest % B;
-    const int64_t p = rest / B;
-    out[idx] = in[a + A * (b + B * (c + C * p))];
+// out[a, c, b, p] = in[a, b, c, p] with A large: a gather of whole rows.  Both
+// tensors are rows of A contiguous elements; output row c + C (b + B p) is
+// input row b + B (c + C p).  Each thread moves one vector V of a row (16
+// bytes when a row is a whole number of 16-byte vectors, else one element),
+// the row index is split once per vector in 32-bit arithmetic (the caller
+// guarantees rows * nv < 2^31; the loop counter itself is 64-bit), so loads
+// and stores run along the rows.
+template <typename V>
+__global__ __launch_bounds__(256) void swap_rows_kernel(const V* __restrict__ in, V* __restrict__ out, int nv,
+                                                        int B, int C, int total) {
+  for (int64_t vv = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; vv < total;
+       vv += (int64_t)gridDim.x * blockDim.x) {
+    const int v = (int)vv;
+    const int ro = v / nv, col = v - ro * nv;
+    const int c = ro % C, t = ro / C;
+    const int b = t % B, p = t / B;
+    const int ri = b + B * (c + C * p);
+    out[(int64_t)ro * nv + col] = in[(int64_t)ri * nv + col];
   }
+}
+
+// the same for tensors past the 32-bit range: 64-bit index arithmetic
+template <typename V>
+__global__ __launch_bounds__(256) void swap_rows64_kernel(const V* __restrict__ in, V* __restrict__ out, int64_t nv,
+                                                          int64_t B, int64_t C, int64_t total) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < total; v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ro = v / nv, col = v - ro * nv;
+    const int64_t c = ro % C, t = ro / C;
+    const int64_t b = t % B, p = t / B;
+    out[ro * nv + col] = in[(b + B * (c + C * p)) * nv + col];
+  }
+}
+
+template <typename V>
+int launch_swap_rows(const void* in, void* out, int64_t nv, int64_t B, int64_t C, int64_t P, hipStream_t s) {
+  const int64_t total = nv * B * C * P;
+  const int grid = (int)std::min<int64_t>(ceil_div(total, 256), 262144);
+  if (total < 0x7fffffff)
+    hipLaunchKernelGGL(swap_rows_kernel<V>, dim3(grid), dim3(256), 0, s, (const V*)in, (V*)out, (int)nv, (int)B,
+                       (int)C, (int)total);
+  else
+    hipLaunchKernelGGL(swap_rows64_kernel<V>, dim3(grid), dim3(256), 0, s, (const V*)in, (V*)out, nv, B, C, total);
+  HPT_LAUNCH_CHECK("swap_rows_kernel");
+  return 0;
 }
 
 // out[a, c, b, p] = in[a, b, c, p] with small A: tile (b, c) planes through LDS.
@@ -120,15 +153,17 @@ int permute_swap_mid(const void* in, void* out, int64_t A, int64_t B, int64_t C,
                      int elem, hipStream_t s) {
   const int64_t total = A * B * C * P;
   if (total == 0) return 0;
-  if (A >= 16 || B == 1 || C == 1) {
-    if (elem == 8)
-      hipLaunchKernelGGL(swap_mid_elem_kernel<uint64_t>, dim3(grid_for(total)), dim3(256), 0, s,
-                         (const uint64_t*)in, (uint64_t*)out, A, B, C, total);
-    else
-      hipLaunchKernelGGL(swap_mid_elem_kernel<uint32_t>, dim3(grid_for(total)), dim3(256), 0, s,
-                         (const uint32_t*)in, (uint32_t*)out, A, B, C, total);
-    HPT_LAUNCH_CHECK("swap_mid_elem_kernel");
+  if (B == 1 || C == 1) {
+    // nothing moves: a plain copy
+    HPT_HIP(hipMemcpyAsync(out, in, (size_t)total * elem, hipMemcpyDeviceToDevice, s));
     return 0;
+  }
+  if (A >= 16) {
+    const int64_t row_bytes = A * elem;
+    const bool vec = row_bytes % 16 == 0 && ((uintptr_t)in & 15) == 0 && ((uintptr_t)out & 15) == 0;
+    if (vec) return launch_swap_rows<uint4>(in, out, row_bytes / 16, B, C, P, s);
+    if (elem == 8) return launch_swap_rows<uint64_t>(in, out, A, B, C, P, s);
+    return launch_swap_rows<uint32_t>(in, out, A, B, C, P, s);
   }
   const int64_t tiles_b = ceil_div(B, TT), tiles_c = ceil_div(C, TT);
   const int64_t slices = A * P;

@@ -58,3 +58,16 @@ def test_bond_classes_of_the_10x10_lattice():
     assert len(cb) == 4
     # horizontal bonds ((3,4),(4,4)) and ((4,4),(5,4)); vertical ((4,3),(4,4)) and ((4,4),(4,5))
     assert cb == [4 * 9 + 3, 4 * 9 + 4, 90 + 3 * 10 + 4, 90 + 4 * 10 + 4]
+
+
+def test_site_bonds_and_measurement_bytes():
+    sys.path.insert(0, ROOT)
+    import bench
+    sb = bench.site_bonds(10)
+    assert sorted(len(l) for l in sb).count(4) == 64 and sorted(len(l) for l in sb).count(2) == 4
+    # every bond appears at its two end sites
+    from collections import Counter
+    cnt = Counter(b for l in sb for b in l)
+    assert set(cnt.values()) == {2} and len(cnt) == 180
+    # all bonds at chi: 64 chi^4 + 32 chi^3 + 4 chi^2 entries
+    assert bench.meas_sweep_bytes([100] * 180, 10, 4) == 4 * (64 * 100 ** 4 + 32 * 100 ** 3 + 4 * 100 ** 2)

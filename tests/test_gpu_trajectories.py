@@ -108,3 +108,18 @@ def test_config1_chi20_trap_retry():
         assert bool(got[k]["flags"] & hpt.FLAGS["TRAP_REMEDIATED"]) == bool(rec["flags"] & hpt.FLAGS["TRAP_REMEDIATED"])
     assert got[-1]["flags"] & hpt.FLAGS["TRAP_REMEDIATED"]
     assert 0.05 < got[-1]["C"] < 0.07
+
+
+def test_zzx_axes_fp64_matches_oracle():
+    # model_axes "zzx" (ZZ coupling, X field, observable Z_c): the library's
+    # trajectory against the oracle's on 3x3 chi 8, 10 layers
+    hpt = load_hpt()
+    from oracle.network import Config
+    from oracle.run import run
+    cfg = dict(Lx=3, Ly=3, J=1.0, h=1.3, dt=0.05, chi_max=8, bp_alpha=0.5, bp_tol=1e-10)
+    recs, _ = run(Config(model_axes="zzx", **cfg), 10)
+    got = _traj(hpt, cfg, 10, model_axes="zzx")
+    for k, rec in enumerate(recs):
+        assert abs(got[k]["C"] - rec["C"]) <= 1e-10, (k, got[k]["C"], rec["C"])
+    paper = _traj(hpt, cfg, 10)
+    assert max(abs(a["C"] - b["C"]) for a, b in zip(got, paper)) > 1e-2
