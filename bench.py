@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--allow-unsaturated", action="store_true",
                     help="do not stop when the centre bonds are below chi_max at the snapshot")
     ap.add_argument("--no-fp64-check", action="store_true", help="skip the FP64 run of the same layers")
+    ap.add_argument("--trace-markers", action="store_true",
+                    help="launch a small torch kernel right before the first and after the last timed layer "
+                         "(window markers for a kernel trace)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x6", "fp64"])
     ap.add_argument("--L", type=int, default=10)
     ap.add_argument("--chi", type=int, default=100)
@@ -558,6 +561,11 @@ def main():
         if timed and not args.profile_all and i == args.warmup:
             hpt.profile_gemm(True)
             sim.phase_timing(True)
+        if timed and i == args.warmup and args.trace_markers:
+            # a distinctive torch kernel before the first timed layer (kernel-trace window marker)
+            torch.cuda.synchronize()
+            torch.full((7,), 3.0, device="cuda").mul_(2.0)
+            torch.cuda.synchronize()
         r = run_layer(sim, torch, f"{args.precision} {'timed' if timed else 'warmup'}", trace)
         at = r["step"]
         assert r["step"] == layer, (r["step"], layer)
@@ -573,6 +581,10 @@ def main():
         if timed:
             elapsed += r["seconds"]
             timed_recs.append(r)
+    if args.trace_markers:
+        torch.cuda.synchronize()
+        torch.full((7,), 3.0, device="cuda").mul_(2.0)
+        torch.cuda.synchronize()
     kinds = {k: hpt.profile_gemm_read(k) for k in hpt.PROF_KINDS}
     hpt.profile_gemm(False)
     phase = sim.phase_read()

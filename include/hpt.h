@@ -380,6 +380,13 @@ int hpt_gram64(const float* X, int64_t m, int32_t n, int64_t ldx, double* G, int
 int hpt_gram64_noalloc(const float* X, int64_t m, int32_t n, int64_t ldx, double* G, int64_t ldg,
                        void* hip_stream);
 
+/* Diagnostic of the split-bf16 products (HPT_FP32_BF16X6): one
+ * v_mfma_f32_16x16x32_bf16 instruction computing, in each of its 256 outputs,
+ * c + sum_{k<32} bf16(a[k]).  a: 32 floats, out: 256 floats (64 lanes x 4
+ * result registers), device.  Shows how the instruction rounds the float32
+ * sum of its products (tests/test_gpu_bsplit_rounding.py). */
+int hpt_bf16_mfma_sum(const float* a, float c, float* out, void* hip_stream);
+
 /* Permute a column-major tensor on the device (Sec. "GPU Tensor Permutation").
  * in/out: device pointers, not overlapping; ndim <= 8; dims of the input;
  * perm[k] = input axis that becomes output axis k; elem_size 4 or 8.

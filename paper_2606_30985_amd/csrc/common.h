@@ -85,6 +85,10 @@ int mode_product_f32(const float* S, const float* src, float* dst, int n, int64_
 int mode_product_f64acc(const double* S, const float* src, float* dst, int n, int64_t inner, int64_t outer,
                         hipStream_t s);
 
+// One bf16 MFMA (16x16x32) summing 32 values a (device, float32, rounded to
+// bf16) onto c in every output (out: 256 floats, device)
+int bf16_mfma_sum(const float* a, float c, float* out, hipStream_t s);
+
 // Leg Gram of the float32 form: out[i, j] (n x n, float64) = sum over a < inner,
 // b < outer of psi[a, i, b] cur[a, j, b] (column-major), float32 MFMA products
 // accumulated per workgroup, float64 partials (part, n^2 per workgroup, at

@@ -631,7 +631,7 @@ int phase_a_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, uint32_t& 
       TriInvJob tj{s->G2, r, r, s->Ri1, r, nullptr};
       TriInvJob* tjd;
       RC(stage(s, &tj, 1, &tjd));
-      KR(launch_tri_inverse(tjd, 1, s->stream));
+      KR(launch_tri_inverse(tjd, 1, s->stream, 4 * s->chi_max));
       SelJob g1{1, s->Ri1, r, s->W1, n, s->sel, r, n};
       RC(stage(s, &g1, 1, &sjd));
       KR(launch_sel(sjd, 1, s->stream));
@@ -656,7 +656,7 @@ int phase_a_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, uint32_t& 
       if (info == 0) {
         TriInvJob tj2{s->R2, r, r, s->Ri2, r, nullptr};
         RC(stage(s, &tj2, 1, &tjd));
-        KR(launch_tri_inverse(tjd, 1, s->stream));
+        KR(launch_tri_inverse(tjd, 1, s->stream, 4 * s->chi_max));
         // R = R2 R1 (r x n, ld 4 chi_max), Rinv = W1 R2^{-1} (n x r)
         SmallGemmJob gj[2];
         std::memset(gj, 0, sizeof(gj));
@@ -770,7 +770,7 @@ int phase_a_batched(hpt_sim* s, std::vector<SitePlan>& plans, uint32_t& flags) {
       KR(launch_sel(sd, ng, s->stream));
       TriInvJob* td;
       RC(stage(s, ti.data(), ng, &td));
-      KR(launch_tri_inverse(td, ng, s->stream));
+      KR(launch_tri_inverse(td, ng, s->stream, 4 * s->chi_max));
       RC(stage(s, sca.data(), ng, &sd));
       KR(launch_sel(sd, ng, s->stream));
       SmallGemmJob* gd;
@@ -810,7 +810,7 @@ int phase_a_batched(hpt_sim* s, std::vector<SitePlan>& plans, uint32_t& flags) {
       }
       if (!t2.empty()) {
         RC(stage(s, t2.data(), (int)t2.size(), &td));
-        KR(launch_tri_inverse(td, (int)t2.size(), s->stream));
+        KR(launch_tri_inverse(td, (int)t2.size(), s->stream, 4 * s->chi_max));
         RC(stage(s, fin.data(), (int)fin.size(), &gd));
         KR(launch_small_gemm(gd, fin.data(), (int)fin.size(), s->stream));
       }
@@ -1036,7 +1036,7 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
     RC(stage(s, c1.data(), nj, &chd));
     KR(launch_cholesky(chd, nj, 1e-10, s->stream));
     RC(stage(s, t1.data(), nj, &tid));
-    KR(launch_tri_inverse(tid, nj, s->stream));
+    KR(launch_tri_inverse(tid, nj, s->stream, 4 * s->chi_max));
     RC(stage(s, g1.data(), nj, &gd));
     KR(launch_small_gemm(gd, g1.data(), nj, s->stream));
     RC(stage(s, g2.data(), nj, &gd));
@@ -1044,7 +1044,7 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
     RC(stage(s, c2.data(), nj, &chd));
     KR(launch_cholesky(chd, nj, 1e-10, s->stream));
     RC(stage(s, t2.data(), nj, &tid));
-    KR(launch_tri_inverse(tid, nj, s->stream));
+    KR(launch_tri_inverse(tid, nj, s->stream, 4 * s->chi_max));
     RC(stage(s, fin.data(), 2 * nj, &gd));
     KR(launch_small_gemm(gd, fin.data(), 2 * nj, s->stream));
   }

@@ -1227,6 +1227,29 @@ int leg_gram_f32(const float* psi, const float* cur, int n, int64_t inner, int64
   return 1;
 }
 
+// One v_mfma_f32_16x16x32_bf16 whose every output is sum_k bf16(a[k]) + c
+// (the same 32 values a in every row, all ones in the other operand): shows
+// how the instruction rounds its float32 sum (out: 64 lanes x 4 registers).
+__global__ void bf16_mfma_sum_kernel(const float* __restrict__ a, float c, float* __restrict__ out) {
+  const int l = threadIdx.x;
+  bf8 x, y;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    x[t] = (__bf16)a[8 * (l / 16) + t];
+    y[t] = (__bf16)1.0f;
+  }
+  f4 acc = {c, c, c, c};
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(y, x, acc, 0, 0, 0);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) out[4 * l + e] = acc[e];
+}
+
+int bf16_mfma_sum(const float* a, float c, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(bf16_mfma_sum_kernel, dim3(1), dim3(64), 0, s, a, c, out);
+  HPT_LAUNCH_CHECK("bf16_mfma_sum_kernel");
+  return 0;
+}
+
 // float64-arithmetic mode product of float32 data: one thread per
 // (a, 8 consecutive j, b), the 8 sums carried in registers over k; consecutive
 // threads take consecutive a, so the loads of src[a, k, b] are coalesced

@@ -560,15 +560,26 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(const SvdJob* jobs) {
 
 // Left-looking upper Cholesky; at step j every later column i needs the dot
 // of columns j and i above row j: one wave per column, lanes over rows.
+// Upper Cholesky G = R^T R, blocked right-looking with 16-column blocks (one
+// workgroup per job, the working matrix in R, L2-resident):
+//   (a) wave 0 factors the diagonal block in registers (lane l holds column
+//       l of the block; the pivot test d > rel_tol * G_jj of the original
+//       diagonal is taken on the updated diagonal, as column by column),
+//   (b) every column j past the block solves R_kk^T x = A[k-block, j],
+//   (c) the trailing upper triangle takes the rank-16 update A -= P^T P in
+//       4 x 4 tiles (P = the block's rows of R).
+// Three barriers per block instead of two per column.
+constexpr int CB = 16;
+
 __global__ __launch_bounds__(1024) void cholesky_kernel(const CholJob* jobs, double rel_tol) {
   const CholJob job = jobs[blockIdx.x];
   if (gated_out(job.gate, job.gate_zero)) return;
   const int n = job.n;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* R = job.R;
-  const int ldr = job.ldr;
+  const int64_t ldr = job.ldr;
   __shared__ double diag0[1024];
-  __shared__ double sh[16];
+  __shared__ double Dk[CB][CB + 1];   // Dk[t][l] = R[k0 + t, k0 + l] of the factored block
   __shared__ int s_fail;
   for (int idx = tid; idx < n * n; idx += blockDim.x) {
     const int i = idx % n, j = idx / n;
@@ -583,22 +594,42 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(const CholJob* jobs, dou
   }
   if (tid == 0) s_fail = 0;
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const double* Rj = R + (int64_t)j * ldr;
-    // pivot: wave 0 reduces the column above the diagonal
+  for (int k0 = 0; k0 < n; k0 += CB) {
+    const int kw = n - k0 < CB ? n - k0 : CB;
+    const int k1 = k0 + kw;
+    // (a) diagonal block in wave 0, in LDS (one wave's LDS operations execute
+    // in order; the fences keep the compiler from reordering them)
     if (wave == 0) {
-      double part = 0.0;
-      for (int k = lane; k < j; k += 64) part += Rj[k] * Rj[k];
-      part = wave_sum(part);
-      if (lane == 0) {
-        const double d = Rj[j] - part;
-        if (!(d > rel_tol * diag0[j]) || !(diag0[j] > 0.0)) {
-          s_fail = j + 1;
-        } else {
-          sh[0] = sqrt(d);
-          R[j + (int64_t)j * ldr] = sh[0];
-        }
+      for (int idx = lane; idx < CB * CB; idx += 64) {
+        const int t = idx % CB, l = idx / CB;
+        Dk[t][l] = (t <= l && l < kw) ? R[k0 + t + (int64_t)(k0 + l) * ldr] : 0.0;
       }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      for (int j = 0; j < kw; ++j) {
+        if (lane == 0) {
+          double part = 0.0;
+          for (int t = 0; t < j; ++t) part += Dk[t][j] * Dk[t][j];
+          const double d = Dk[j][j] - part;
+          const double g0 = diag0[k0 + j];
+          if (!(d > rel_tol * g0) || !(g0 > 0.0))
+            s_fail = k0 + j + 1;
+          else
+            Dk[j][j] = sqrt(d);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        if (s_fail) break;
+        if (lane > j && lane < kw) {
+          double part = 0.0;
+          for (int t = 0; t < j; ++t) part += Dk[t][j] * Dk[t][lane];
+          Dk[j][lane] = (Dk[j][lane] - part) / Dk[j][j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      }
+      if (!s_fail)
+        for (int idx = lane; idx < CB * CB; idx += 64) {
+          const int t = idx % CB, l = idx / CB;
+          if (t <= l && l < kw) R[k0 + t + (int64_t)(k0 + l) * ldr] = Dk[t][l];
+        }
     }
     __syncthreads();
     if (s_fail) {
@@ -608,13 +639,72 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(const CholJob* jobs, dou
       }
       return;
     }
-    const double rjj = sh[0];
-    for (int i = j + 1 + wave; i < n; i += nw) {
-      const double* Ri = R + (int64_t)i * ldr;
-      double part = 0.0;
-      for (int k = lane; k < j; k += 64) part += Rj[k] * Ri[k];
-      part = wave_sum(part);
-      if (lane == 0) R[j + (int64_t)i * ldr] = (Ri[j] - part) / rjj;
+    // (b) panel: R[k-block, j] = R_kk^-T A[k-block, j] for j >= k1
+    for (int j = k1 + tid; j < n; j += blockDim.x) {
+      double* c = R + k0 + (int64_t)j * ldr;
+      double x[CB];
+      // an opaque zero keeps the block's reads inside this loop (hoisted out
+      // of it, the 136 values would not fit the registers)
+      int opq = 0;
+      asm volatile("" : "+v"(opq));
+      const double* D = &Dk[0][0] + opq;
+#pragma unroll
+      for (int t = 0; t < CB; ++t) {
+        if (t < kw) {
+          double a = c[t];
+#pragma unroll
+          for (int u = 0; u < t; ++u) a -= D[u * (CB + 1) + t] * x[u];
+          x[t] = a / D[t * (CB + 1) + t];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < CB; ++t)
+        if (t < kw) c[t] = x[t];
+    }
+    __syncthreads();
+    // (c) trailing update of the upper triangle, 4 x 4 tiles (ti <= tj)
+    const int m = n - k1;
+    if (m > 0) {
+      const int T = (m + 3) / 4;
+      const int ntiles = T * (T + 1) / 2;
+      for (int q = tid; q < ntiles; q += blockDim.x) {
+        // tile index -> (ti, tj) with ti <= tj, column by column
+        int tj = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+        while ((tj + 1) * (tj + 2) / 2 <= q) ++tj;
+        while (tj * (tj + 1) / 2 > q) --tj;
+        const int ti = q - tj * (tj + 1) / 2;
+        const int i0 = k1 + 4 * ti, j0 = k1 + 4 * tj;
+        double acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+#pragma unroll 2
+        for (int t = 0; t < kw; ++t) {
+          {
+            double pi[4], pj[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              pi[a] = i0 + a < n ? R[k0 + t + (int64_t)(i0 + a) * ldr] : 0.0;
+              pj[a] = j0 + a < n ? R[k0 + t + (int64_t)(j0 + a) * ldr] : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+              for (int b = 0; b < 4; ++b) acc[a][b] += pi[a] * pj[b];
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int j = j0 + b;
+          if (j >= n) continue;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const int i = i0 + a;
+            if (i <= j) R[i + (int64_t)j * ldr] -= acc[a][b];
+          }
+        }
+      }
     }
     __syncthreads();
   }
@@ -738,31 +828,84 @@ __global__ void sel_kernel(const SelJob* jobs) {
 // column c of Y follows from forward substitution with the columns of R
 // (contiguous reads); one wave per column, lanes over the inner index.
 // Rinv = Y^T.
+// X = R^-1 of an upper-triangular n x n R (n <= 1024), by block rows from
+// the bottom: X[I, :] = R_II^-1 (E[I, :] - sum_{K > I} R_IK X[K, :]) with
+// 16-row blocks.  Per block row: its rows of R staged in LDS, the 16 x 16
+// inverse of R_II built by 16 threads (one column each), then one thread per
+// column j of X forms the 16 sums over k in (block, j] and the block row.
+// Three barriers per block row instead of a reduction per entry.
+constexpr int TB = 16;
+
 __global__ __launch_bounds__(1024) void tri_inverse_kernel(const TriInvJob* jobs) {
   const TriInvJob job = jobs[blockIdx.x];
   if (gated_out(job.gate, job.gate_zero)) return;
   const int n = job.n;
   const double* R = job.R;
-  double* Ri = job.Ri;
-  const int ldr = job.ldr, ldi = job.ldri;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-  __shared__ double ybuf[16][1024];
-  double* y = ybuf[wave];
+  double* X = job.Ri;
+  const int64_t ldr = job.ldr, ldi = job.ldri;
+  const int tid = threadIdx.x;
+  extern __shared__ double tlds[];
+  double* Rs = tlds;                    // Rs[t * n + k] = R[r0 + t, k], k >= r0
+  double* RI = tlds + TB * n;           // RI[t * (TB + 1) + u] = (R_II^-1)[t, u]
   for (int idx = tid; idx < n * n; idx += blockDim.x) {
     const int i = idx % n, c = idx / n;
-    if (i > c) Ri[i + (int64_t)c * ldi] = 0.0;
+    if (i > c) X[i + (int64_t)c * ldi] = 0.0;
   }
-  for (int c = wave; c < n; c += nw) {
-    // y[i] for i >= c: y[c] = 1/R[c,c]; y[i] = -(sum_{c<=k<i} R[k,i] y[k]) / R[i,i]
-    if (lane == 0) y[c] = 1.0 / R[c + (int64_t)c * ldr];
-    for (int i = c + 1; i < n; ++i) {
-      const double* Rc = R + (int64_t)i * ldr;
-      double part = 0.0;
-      for (int k = c + lane; k < i; k += 64) part += Rc[k] * y[k];
-      part = wave_sum(part);
-      if (lane == 0) y[i] = -part / Rc[i];
+  const int nb = (n + TB - 1) / TB;
+  for (int I = nb - 1; I >= 0; --I) {
+    const int r0 = I * TB, kw = n - r0 < TB ? n - r0 : TB, r1 = r0 + kw;
+    for (int idx = tid; idx < kw * (n - r0); idx += blockDim.x) {
+      const int t = idx % kw, k = r0 + idx / kw;
+      Rs[t * n + k] = R[r0 + t + (int64_t)k * ldr];
     }
-    for (int i = c + lane; i < n; i += 64) Ri[c + (int64_t)i * ldi] = y[i];
+    __syncthreads();
+    if (tid < kw) {
+      // column u = tid of R_II^-1: back substitution on R_II y = e_u
+      const int u = tid;
+      double y[TB];
+#pragma unroll
+      for (int t = TB - 1; t >= 0; --t) {
+        double v = 0.0;
+        if (t <= u) {
+          double acc = (t == u) ? 1.0 : 0.0;
+#pragma unroll
+          for (int q = t + 1; q < TB; ++q)
+            if (q <= u) acc -= Rs[t * n + r0 + q] * y[q];
+          v = acc / Rs[t * n + r0 + t];
+        }
+        y[t] = v;
+      }
+#pragma unroll
+      for (int t = 0; t < TB; ++t)
+        if (t < kw) RI[t * (TB + 1) + u] = y[t];
+    }
+    __syncthreads();
+    for (int j = r0 + tid; j < n; j += blockDim.x) {
+      double S[TB];
+#pragma unroll
+      for (int t = 0; t < TB; ++t) S[t] = 0.0;
+      // S[t] = sum over k in [r1, j] of R[r0 + t, k] X[k, j]
+      for (int k = r1; k <= j; ++k) {
+        const double x = X[k + (int64_t)j * ldi];
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+          if (t < kw) S[t] += Rs[t * n + k] * x;
+      }
+      double e[TB];
+#pragma unroll
+      for (int u = 0; u < TB; ++u) e[u] = (r0 + u == j ? 1.0 : 0.0) - S[u];
+#pragma unroll
+      for (int t = 0; t < TB; ++t) {
+        if (t < kw && r0 + t <= j) {
+          double v = 0.0;
+#pragma unroll
+          for (int u = 0; u < TB; ++u)
+            if (u >= t && u < kw) v += RI[t * (TB + 1) + u] * e[u];
+          X[r0 + t + (int64_t)j * ldi] = v;
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -951,9 +1094,18 @@ int launch_cholesky(const CholJob* jobs, int njobs, double rel_tol, hipStream_t 
   return 0;
 }
 
-int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s) {
+int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s, int nmax) {
   if (njobs <= 0) return 0;
-  hipLaunchKernelGGL(tri_inverse_kernel, dim3(njobs), dim3(1024), 0, s, jobs);
+  if (nmax < 1 || nmax > 1024) return -1;
+  const size_t lds = (size_t)(TB * nmax + TB * (TB + 1)) * sizeof(double);
+  static int max_lds = 0;
+  if (!max_lds) {
+    int dev = 0;
+    HPT_HIP(hipGetDevice(&dev));
+    HPT_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  }
+  if (lds > (size_t)max_lds) return -1;
+  hipLaunchKernelGGL(tri_inverse_kernel, dim3(njobs), dim3(1024), lds, s, jobs);
   HPT_LAUNCH_CHECK("tri_inverse_kernel");
   return 0;
 }

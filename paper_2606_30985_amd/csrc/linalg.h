@@ -117,7 +117,8 @@ int launch_jacobi_svd(const SvdJob* jobs, int njobs, hipStream_t s);
 int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, hipStream_t s, int* done_dev,
                             volatile int* done_host, int max_sweeps = 20);
 int launch_cholesky(const CholJob* jobs, int njobs, double rel_tol, hipStream_t s);
-int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s);
+// nmax: largest n of the jobs (<= 1024; sizes the LDS staging)
+int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s, int nmax);
 int launch_piv_cholesky(const PivCholJob* jobs, int njobs, hipStream_t s);
 int launch_sel(const SelJob* jobs, int njobs, hipStream_t s);
 int launch_small_gemm(const SmallGemmJob* jobs, const SmallGemmJob* host, int njobs, hipStream_t s);

@@ -93,6 +93,11 @@ int hpt_learn_adam(float* params, float* m, float* v, const float* grad, int32_t
   return launch_learn_adam(params, m, v, grad, step, lr, (hipStream_t)hip_stream) ? HPT_EHIP : HPT_OK;
 }
 
+int hpt_bf16_mfma_sum(const float* a, float c, float* out, void* hip_stream) {
+  if (!a || !out) return HPT_EINVAL;
+  return bf16_mfma_sum(a, c, out, (hipStream_t)hip_stream) ? HPT_EHIP : HPT_OK;
+}
+
 int hpt_gram64_noalloc(const float* X, int64_t m, int32_t n, int64_t ldx, double* G, int64_t ldg,
                        void* hip_stream) {
   int splits = 0;

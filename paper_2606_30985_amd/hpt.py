@@ -125,6 +125,7 @@ def _load():
         "hpt_learn_forward": [P, P, ctypes.c_int64, P, P],
         "hpt_learn_backward": [P, P, P, P, ctypes.c_int64, P, P],
         "hpt_learn_adam": [P, P, P, P, i32, ctypes.c_float, P],
+        "hpt_bf16_mfma_sum": [P, ctypes.c_float, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -148,7 +149,7 @@ EXPORTED = ["hpt_config_default", "hpt_required_bytes", "hpt_state_bytes", "hpt_
             "hpt_checkpoint_bytes", "hpt_checkpoint_save", "hpt_checkpoint_load", "hpt_phase_timing",
             "hpt_phase_read", "hpt_gram64_workspace_bytes", "hpt_gram64", "hpt_gram64_noalloc",
             "hpt_meas_learn_rows", "hpt_meas_features", "hpt_meas_targets", "hpt_set_meas_model",
-            "hpt_learn_forward", "hpt_learn_backward", "hpt_learn_adam"]
+            "hpt_learn_forward", "hpt_learn_backward", "hpt_learn_adam", "hpt_bf16_mfma_sum"]
 
 HPT_MEM_HOST = 0
 HPT_MEM_DEVICE = 1
