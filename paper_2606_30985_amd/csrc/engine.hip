@@ -1345,11 +1345,12 @@ int meas_outgoing(hpt_sim* s, bool only_first_leg) {
   int64_t used = 0, pused = 0;
   auto flush = [&]() -> int {
     if (!ll.empty()) {
-      const int64_t blocks = last_leg_plan(ll.data(), (int)ll.size());
+      int max_nl = 1;
+      const int64_t blocks = last_leg_plan(ll.data(), (int)ll.size(), s->fp32 ? 0 : 1, &max_nl);
       if (blocks < 0) return HPT_EINVAL;
       LastLegJob* ld;
       RC(stage(s, ll.data(), (int)ll.size(), &ld));
-      KR(launch_last_leg(ld, (int)ll.size(), blocks, s->fp32 ? 0 : 1, s->stream));
+      KR(launch_last_leg(ld, (int)ll.size(), blocks, max_nl, s->fp32 ? 0 : 1, s->stream));
     }
     if (!batch.empty()) {
       int64_t totals[4];
@@ -1390,7 +1391,8 @@ int meas_outgoing(hpt_sim* s, bool only_first_leg) {
     lj.mL = in_msg(si, L);
     lj.out = out_msg(si, v, L);
     std::vector<MeasJob> js;
-    int64_t need = rows + last_leg_blocks(rows) * dims[L], pjob = 0;
+    const int64_t llb = last_leg_blocks(rows, s->fp32 ? 0 : 1);
+    int64_t need = rows + llb * dims[L], pjob = 0;
     for (int k = 0; k < L; ++k) {
       if (only_first_leg && k > 0) break;
       MeasJob j;
@@ -1419,7 +1421,7 @@ int meas_outgoing(hpt_sim* s, bool only_first_leg) {
       RC(flush());
     lj.P = s->meas_scr + used;
     lj.part = lj.P + rows;
-    used += rows + last_leg_blocks(rows) * dims[L];
+    used += rows + llb * dims[L];
     ll.push_back(lj);
     for (MeasJob& j : js) {
       j.T = lj.P;

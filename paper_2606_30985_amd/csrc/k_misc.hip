@@ -3,6 +3,7 @@
 // contractions of the pinned network (Sec. "Correlation Function via Belief
 // Propagation", Eq. bethe_raw), the log-space sum with sign tracking
 // (Eq. bethe), and the projections used by the gauge-sign rule.
+#include <algorithm>
 #include "misc.h"
 #include "wave.h"
 
@@ -261,8 +262,27 @@ __global__ void meas_gemv_t_reduce(const MeasJob* jobs, const double* part) {
   }
 }
 
-constexpr int LL_ROWS = 1024;   // rows per block: 4 waves x 64 lanes x 4 rows
+// Rows per lane of the last-leg kernel: NV 16-byte vectors (4 floats or 2
+// doubles each) per column; a block of 256 lanes covers 256 x that many rows.
+// Three float vectors per lane (12 rows) measured best on the 10x10 chi=100
+// sweep: two pay twice the per-column wave reductions, four need 180 VGPRs
+// (two waves per SIMD) and leave fewer bytes in flight.  The kernel is held
+// to 128 VGPRs (four waves per SIMD, no spills), 7% faster than 130.
 constexpr int LL_MAXL = 1024;
+template <typename T> struct LLShape {
+  static constexpr int V = 16 / (int)sizeof(T);   // rows per vector
+  static constexpr int NV = sizeof(T) == 4 ? 3 : 2;
+  static constexpr int R = V * NV;                // rows per lane
+  static constexpr int BR = 256 * R;              // rows per block
+};
+// 16-byte vectors in the global address space (plain global loads, waited on
+// by the vector-memory counter alone)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = f32x4; };
+template <> struct Vec16<double> { using type = f64x2; };
+#define HPT_GLOBAL __attribute__((address_space(1)))
 
 __device__ inline int find_ll(const LastLegJob* jobs, int njobs, int64_t b) {
   int lo = 0, hi = njobs - 1;
@@ -273,81 +293,152 @@ __device__ inline int find_ll(const LastLegJob* jobs, int njobs, int64_t b) {
   return lo;
 }
 
-// each lane owns 4 rows (stride 256); for every column e the lane's rows are
-// read once (coalesced along r), folded into P and into the wave's partial of
-// out[e]
+// Column loop of the last-leg kernel for one block.  VEC: the slice allows
+// 16-byte loads (aligned base, rows a multiple of V); FULL: every row of the
+// block is inside the slice, so no row guards.  All variants fold the same
+// rows in the same order, so they give equal bits.
+template <typename T, bool VEC, bool FULL>
+__device__ __forceinline__ void ll_columns(const double* mL, const T* Tp, int rows, int nL,
+                                           int rb, const double (&xr)[LLShape<T>::NV][LLShape<T>::V],
+                                           double (&pacc)[LLShape<T>::NV][LLShape<T>::V],
+                                           double* wp, int lane, int wave) {
+  using S = LLShape<T>;
+  constexpr int V = S::V, NV = S::NV;
+  using VecT = typename Vec16<T>::type;
+  typedef const T HPT_GLOBAL* GP;
+  typedef const VecT HPT_GLOBAL* GVP;
+  GP base = (GP)Tp + rb;   // this lane's first row of column 0
+  auto load = [&](int e, T (&t)[NV][V]) {
+    GP col = base + (int64_t)rows * e;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const bool in = FULL || rb + k * 64 * V < rows;
+      if (VEC) {
+        VecT x;
+        if (in) x = *(GVP)(col + k * 64 * V);
+        else x = VecT(0);
+#pragma unroll
+        for (int j = 0; j < V; ++j) t[k][j] = x[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          t[k][j] = (FULL || rb + k * 64 * V + j < rows) ? col[k * 64 * V + j] : T(0);
+      }
+    }
+  };
+  auto fold = [&](int e, const T (&t)[NV][V]) {
+    const double me = mL[e];
+    double sk[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const double x = (double)t[k][j];
+        pacc[k][j] += x * me;
+        s += x * xr[k][j];
+      }
+      sk[k] = s;
+    }
+    double s = sk[0];
+#pragma unroll
+    for (int k = 1; k < NV; ++k) s += sk[k];
+    s = wave_sum(s);
+    if (lane == 0) wp[wave * nL + e] = s;
+  };
+  // two register buffers; the prefetches in the loop are unconditional, so
+  // each wait before a fold leaves the next column's loads in flight
+  T a[NV][V], b[NV][V];
+  load(0, a);
+  int e = 0;
+  for (; e + 3 <= nL; e += 2) {
+    load(e + 1, b);
+    fold(e, a);
+    load(e + 2, a);
+    fold(e + 1, b);
+  }
+  if (e + 2 == nL) {
+    load(e + 1, b);
+    fold(e, a);
+    fold(e + 1, b);
+  } else {
+    fold(e, a);
+  }
+}
+
+// One pass over the column-major slice T (rows x nL): out-partials
+// part[blk, e] = sum_r T[r, e] x(r) with x the product of the other legs'
+// messages, and P[r] = sum_e T[r, e] mL[e].  Lane vector k covers V
+// consecutive rows; the 64 lanes of a wave read 1 KB contiguous per vector, a
+// column is read as NV such vectors per lane and the next column's loads
+// are issued before the current one is folded.  Per column each wave reduces
+// its 64 lane sums once (DPP), so the reduction is paid once per 64 x R rows.
 template <typename T>
-__global__ __launch_bounds__(256) void last_leg_kernel(const LastLegJob* jobs, int njobs) {
+__global__ __launch_bounds__(256, 4) void last_leg_kernel(const LastLegJob* jobs, int njobs) {
+  using S = LLShape<T>;
+  constexpr int V = S::V, NV = S::NV;
+  // LDS: the 4 waves' column sums [4][nL], then the last leg's message (read
+  // from LDS so that waiting for it never waits for the column loads in flight)
+  extern __shared__ double wp[];
   const LastLegJob& job = jobs[find_ll(jobs, njobs, blockIdx.x)];
-  const int64_t blk = blockIdx.x - job.b0;
+  const int blk = (int)(blockIdx.x - job.b0);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __shared__ double wp[4][LL_MAXL];
-  const int64_t rows = job.rows;
+  const int rows = (int)job.rows;
   const int nL = job.nL;
   const T* Tp = (const T*)job.T;
-  double xr[4], pacc[4];
-  int64_t rr[4];
+  const bool vec = ((reinterpret_cast<uintptr_t>(Tp) & 15) == 0) && (rows % V == 0);
+  const bool full = (int64_t)(blk + 1) * S::BR <= rows;
+  const int rb = blk * S::BR + wave * (64 * S::R) + lane * V;
+
+  double xr[NV][V], pacc[NV][V];
+  const int nx = job.nx;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t r = blk * LL_ROWS + q * 256 + threadIdx.x;
-    rr[q] = r;
-    pacc[q] = 0.0;
-    double v = 0.0;
-    if (r < rows) {
-      v = 1.0;
-      int64_t rem = r;
-      for (int l = 0; l < job.nx; ++l) {
-        v *= job.xm[l][rem % job.xd[l]];
+  for (int k = 0; k < NV; ++k) {
+    const int r0 = rb + k * 64 * V;
+    int idx[3] = {0, 0, 0};
+    if (r0 < rows) {
+      int rem = r0;
+      for (int l = 0; l < nx; ++l) {
+        idx[l] = rem % job.xd[l];
         rem /= job.xd[l];
       }
     }
-    xr[q] = v;
-  }
-  // columns in groups of four: the 16 loads of a group are issued together
-  // (more bytes in flight per wave), then folded and reduced column by column
-  int e = 0;
-  for (; e + 4 <= nL; e += 4) {
-    double t[4][4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const T* col = Tp + rows * (e + c);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) t[c][q] = rr[q] < rows ? (double)col[rr[q]] : 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const double me = job.mL[e + c];
-      double sacc = 0.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        pacc[q] += t[c][q] * me;
-        sacc += t[c][q] * xr[q];
+    for (int j = 0; j < V; ++j) {
+      pacc[k][j] = 0.0;
+      double v = 0.0;
+      if (r0 + j < rows) {
+        v = 1.0;
+        for (int l = 0; l < nx; ++l) v *= job.xm[l][idx[l]];
+        // next row: first leg fastest, carry into the slower legs
+        for (int l = 0; l < nx; ++l) {
+          if (++idx[l] < job.xd[l]) break;
+          idx[l] = 0;
+        }
       }
-      sacc = wave_sum(sacc);
-      if (lane == 0) wp[wave][e + c] = sacc;
+      xr[k][j] = v;
     }
   }
-  for (; e < nL; ++e) {
-    const double me = job.mL[e];
-    const T* col = Tp + rows * e;
-    double sacc = 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (rr[q] < rows) {
-        const double t = (double)col[rr[q]];
-        pacc[q] += t * me;
-        sacc += t * xr[q];
-      }
-    }
-    sacc = wave_sum(sacc);
-    if (lane == 0) wp[wave][e] = sacc;
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (rr[q] < rows) job.P[rr[q]] = pacc[q];
+
+  double* ml = wp + 4 * nL;
+  for (int c = threadIdx.x; c < nL; c += blockDim.x) ml[c] = job.mL[c];
   __syncthreads();
-  for (int e = threadIdx.x; e < nL; e += blockDim.x)
-    job.part[blk * nL + e] = (wp[0][e] + wp[1][e]) + (wp[2][e] + wp[3][e]);
+  if (vec && full) ll_columns<T, true, true>(ml, Tp, rows, nL, rb, xr, pacc, wp, lane, wave);
+  else if (vec) ll_columns<T, true, false>(ml, Tp, rows, nL, rb, xr, pacc, wp, lane, wave);
+  else ll_columns<T, false, false>(ml, Tp, rows, nL, rb, xr, pacc, wp, lane, wave);
+
+  double HPT_GLOBAL* P = (double HPT_GLOBAL*)job.P;
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int r = rb + k * 64 * V + j;
+      if (r < rows) P[r] = pacc[k][j];
+    }
+  __syncthreads();
+  for (int c = threadIdx.x; c < nL; c += blockDim.x)
+    job.part[(int64_t)blk * nL + c] =
+        (wp[c] + wp[nL + c]) + (wp[2 * nL + c] + wp[3 * nL + c]);
 }
 
 // out[e] = sum over blocks of part[blk, e]: 8 groups of 128 columns, fixed order
@@ -526,26 +617,37 @@ int launch_log_product(const double* x, int n_num, int n_den, const double* delt
   return 0;
 }
 
-int64_t last_leg_blocks(int64_t rows) { return ceil_div(rows, LL_ROWS); }
+int64_t last_leg_blocks(int64_t rows, int is_double) {
+  return ceil_div(rows, is_double ? LLShape<double>::BR : LLShape<float>::BR);
+}
 
-int64_t last_leg_plan(LastLegJob* jobs, int njobs) {
+int64_t last_leg_plan(LastLegJob* jobs, int njobs, int is_double, int* max_nl) {
   int64_t b = 0;
+  int ml = 1;
+  const int64_t br = is_double ? LLShape<double>::BR : LLShape<float>::BR;
   for (int j = 0; j < njobs; ++j) {
-    if (jobs[j].nL < 1 || jobs[j].nL > LL_MAXL || jobs[j].rows < 1) return -1;
+    // row indices are 32-bit inside the kernel (rows of the last block included)
+    if (jobs[j].nL < 1 || jobs[j].nL > LL_MAXL || jobs[j].rows < 1 ||
+        jobs[j].rows > 0x7fffffffll - br || jobs[j].nx < 0 || jobs[j].nx > 3)
+      return -1;
     jobs[j].b0 = b;
-    jobs[j].nblk = ceil_div(jobs[j].rows, LL_ROWS);
+    jobs[j].nblk = last_leg_blocks(jobs[j].rows, is_double);
     b += jobs[j].nblk;
+    ml = std::max(ml, jobs[j].nL);
   }
+  if (max_nl) *max_nl = ml;
   return b > 0x7fffffffll ? -1 : b;
 }
 
-int launch_last_leg(const LastLegJob* jobs_dev, int njobs, int64_t blocks, int is_double, hipStream_t s) {
+int launch_last_leg(const LastLegJob* jobs_dev, int njobs, int64_t blocks, int max_nl,
+                    int is_double, hipStream_t s) {
   if (njobs <= 0) return 0;
-  if (blocks < 1 || blocks > 0x7fffffffll) return -1;
+  if (blocks < 1 || blocks > 0x7fffffffll || max_nl < 1 || max_nl > LL_MAXL) return -1;
+  const size_t lds = (size_t)5 * max_nl * sizeof(double);
   if (is_double)
-    hipLaunchKernelGGL(last_leg_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, jobs_dev, njobs);
+    hipLaunchKernelGGL(last_leg_kernel<double>, dim3((unsigned)blocks), dim3(256), lds, s, jobs_dev, njobs);
   else
-    hipLaunchKernelGGL(last_leg_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, jobs_dev, njobs);
+    hipLaunchKernelGGL(last_leg_kernel<float>, dim3((unsigned)blocks), dim3(256), lds, s, jobs_dev, njobs);
   HPT_LAUNCH_CHECK("last_leg_kernel");
   hipLaunchKernelGGL(last_leg_reduce, dim3(njobs), dim3(1024), 0, s, jobs_dev);
   HPT_LAUNCH_CHECK("last_leg_reduce");

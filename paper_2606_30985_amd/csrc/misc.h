@@ -87,11 +87,12 @@ struct LastLegJob {
   int64_t nblk, b0;    // blocks of this job, first block in the launch (set by the launcher)
 };
 // blocks (rows of the partial buffer) a job of `rows` rows needs
-int64_t last_leg_blocks(int64_t rows);
-// fills b0 / nblk of the host jobs; returns the launch's block count, -1 if
-// a job is out of range (nL > 1024)
-int64_t last_leg_plan(LastLegJob* jobs_host, int njobs);
-int launch_last_leg(const LastLegJob* jobs_dev, int njobs, int64_t blocks, int is_double, hipStream_t s);
+int64_t last_leg_blocks(int64_t rows, int is_double);
+// fills b0 / nblk of the host jobs and the largest nL; returns the launch's
+// block count, -1 if a job is out of range (nL > 1024, rows >= 2^31 - block)
+int64_t last_leg_plan(LastLegJob* jobs_host, int njobs, int is_double, int* max_nl);
+int launch_last_leg(const LastLegJob* jobs_dev, int njobs, int64_t blocks, int max_nl,
+                    int is_double, hipStream_t s);
 
 // normalise, sign continuity, damp, normalise; delta[i] = max |mn - mo|
 struct MeasNormJob {
