@@ -513,6 +513,114 @@ __global__ __launch_bounds__(256) void tile_gemm_kernel(const float* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Plain float32 products C = A B (A M x K, B K x N, column-major) in the same
+// 128 x 80 XCD-ordered tiles, f32 16x16x4 MFMA, k-chunks of 32.  Staging:
+// A as float4 along rows (thread: 4 rows, k = kr + 8 g for g = 0..3), kept in
+// LDS as k-rows of 144 floats (row-contiguous; 144 = 16 mod 64, so the four
+// k-rows of an operand read use disjoint banks); B as float4 along k (eight
+// threads per 32-k column segment), kept as columns of 36 floats.  Interior
+// tiles and whole k-chunks of aligned operands take branch-free 16-byte
+// loads; edge tiles and the last partial chunk take guarded element loads
+// into the same layout.  The next chunk is fetched into registers while the
+// current one feeds the MFMAs.
+constexpr int F_SA = 144, F_SB = 36;
+
+__global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__ A, int64_t lda,
+                                                       const float* __restrict__ B, int64_t ldb,
+                                                       float* __restrict__ C, int64_t ldc, int M, int N, int K,
+                                                       int ntn, int64_t total, int64_t per_xcd, int avec,
+                                                       int bvec) {
+  constexpr int BM = BS_BM, BN = BS_BN, KC = BS_KC, SA = F_SA, SB = F_SB;
+  __shared__ __attribute__((aligned(16))) float As[KC * SA];
+  __shared__ __attribute__((aligned(16))) float Bs[BN * SB];
+  const int64_t T = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (T >= total) return;
+  const int row0 = (int)(T / ntn) * BM, col0 = (int)(T % ntn) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int q = tid & 31, kr = tid >> 5;   // A: rows 4q..4q+3, k-rows kr + 8 g
+  const bool a_full = avec && row0 + BM <= M;
+  const bool b_full = bvec && col0 + BN <= N;
+  constexpr int NBU = BN * (KC / 4);       // B float4 units per chunk (640)
+  float4 ra[4], rb[3];
+  auto load = [&](int k0) {
+    const bool kfull = k0 + KC <= K;
+    if (a_full && kfull) {
+      const float* ap = A + row0 + 4 * q + (int64_t)(k0 + kr) * lda;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) ra[g] = *(const float4*)(ap + (int64_t)(8 * g) * lda);
+    } else {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int k = k0 + kr + 8 * g;
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = row0 + 4 * q + e;
+          v[e] = (r < M && k < K) ? A[r + (int64_t)k * lda] : 0.f;
+        }
+        ra[g] = make_float4(v[0], v[1], v[2], v[3]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int u = tid + 256 * t;
+      if (u >= NBU) break;
+      const int c = col0 + (u >> 3), k = k0 + 4 * (u & 7);
+      if (b_full && kfull) {
+        rb[t] = *(const float4*)(B + k + (int64_t)c * ldb);
+      } else {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (c < N && k + e < K) ? B[k + e + (int64_t)c * ldb] : 0.f;
+        rb[t] = make_float4(v[0], v[1], v[2], v[3]);
+      }
+    }
+  };
+  f4 acc[2][5];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  const int nchunks = (K + KC - 1) / KC;
+  load(0);
+  for (int ch = 0; ch < nchunks; ++ch) {
+    __syncthreads();   // every wave is done reading the previous chunk
+#pragma unroll
+    for (int g = 0; g < 4; ++g) *(float4*)(As + (kr + 8 * g) * SA + 4 * q) = ra[g];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int u = tid + 256 * t;
+      if (u < NBU) *(float4*)(Bs + (u >> 3) * SB + 4 * (u & 7)) = rb[t];
+    }
+    __syncthreads();
+    if (ch + 1 < nchunks) load((ch + 1) * KC);
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const int ko = 4 * kk + (lane >> 4);
+      float af[2], bf[5];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) af[i] = As[ko * SA + 32 * w + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 5; ++j) bf[j] = Bs[(16 * j + (lane & 15)) * SB + ko];
+#pragma unroll
+      for (int j = 0; j < 5; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) acc[i][j] = mfma_op(bf[j], af[i], acc[i][j]);
+    }
+  }
+  // register e of block (i, j): C[row 32 w + 16 i + lane % 16, column 16 j + 4 (lane / 16) + e]
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = row0 + 32 * w + 16 * i + (lane & 15), cc = col0 + 16 * j + 4 * (lane >> 4) + e;
+        if (r < M && cc < N) C[r + (int64_t)cc * ldc] = acc[i][j][e];
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Mode products of the float32 form with the n x n factor resident in LDS
 // (n <= 128), persistent workgroups of 4 waves, each wave streaming 16-row
 // (or 16-column) strips of the tensor straight from HBM into MFMA operands.
@@ -1059,9 +1167,11 @@ int tile_gemm(const GemmDesc<float>& d, hipStream_t s) {
                        d.M, d.N, d.K, ntn, total, per_xcd);
     HPT_LAUNCH_CHECK("tile_gemm_kernel<split>");
   } else {
-    hipLaunchKernelGGL(tile_gemm_kernel<false>, grid, dim3(256), 0, s, d.A, d.lda, d.B, d.ldb, (float*)d.C, d.ldc,
-                       d.M, d.N, d.K, ntn, total, per_xcd);
-    HPT_LAUNCH_CHECK("tile_gemm_kernel<float>");
+    const int avec = ((reinterpret_cast<uintptr_t>(d.A) & 15) == 0) && d.lda % 4 == 0;
+    const int bvec = ((reinterpret_cast<uintptr_t>(d.B) & 15) == 0) && d.ldb % 4 == 0;
+    hipLaunchKernelGGL(gemm_f32_kernel, grid, dim3(256), 0, s, d.A, d.lda, d.B, d.ldb, (float*)d.C, d.ldc,
+                       d.M, d.N, d.K, ntn, total, per_xcd, avec, bvec);
+    HPT_LAUNCH_CHECK("gemm_f32_kernel");
   }
   const double M = d.M, N = d.N, K = d.K;
   RC_PROF(prof_end(s, d.bsplit ? 4 : 0, 2.0 * M * N * K, 4.0 * (M * K + K * N + M * N)));

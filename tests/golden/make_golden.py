@@ -21,7 +21,7 @@ CASES = {
     # chi_max 40 and 60: the first layers (the centre bonds reach chi_max by layer ~10 at 40 and
     # ~12 at 60; the full 40-layer runs take hours in the oracle)
     "oracle_4x4_chi40": (dict(Lx=4, Ly=4, J=1.0, h=1.0, dt=0.05, chi_max=40, bp_alpha=0.5, bp_tol=1e-10), 14),
-    "oracle_4x4_chi60": (dict(Lx=4, Ly=4, J=1.0, h=1.0, dt=0.05, chi_max=60, bp_alpha=0.5, bp_tol=1e-10), 12),
+    "oracle_4x4_chi60": (dict(Lx=4, Ly=4, J=1.0, h=1.0, dt=0.05, chi_max=60, bp_alpha=0.5, bp_tol=1e-10), 9),
     "oracle_3x3_chi8": (dict(Lx=3, Ly=3, J=1.0, h=1.0, dt=0.05, chi_max=8, bp_alpha=0.5, bp_tol=1e-10), 20),
     # 10x10 (the benchmark lattice) at chi_max 30, FP64 cutoff, the benchmark's BP settings, 12 layers
     "oracle_10x10_chi30": (dict(Lx=10, Ly=10, J=1.0, h=1.0, dt=0.05, chi_max=30, bp_alpha=0.5, bp_tol=1e-5,

@@ -54,6 +54,33 @@ def test_config1_chi20_fp64_vs_golden():
         assert abs(got[k]["C"] - rec["C"]) <= 1e-10, (k, got[k]["C"], rec["C"])
 
 
+# 4x4 at chi_max 40 and 60: the centre bonds reach chi_max inside the recorded
+# layers (layer 7 at 40), after which every gate truncates
+@pytest.mark.parametrize("name", ["oracle_4x4_chi40", "oracle_4x4_chi60"])
+def test_saturating_chi_fp64_vs_golden(name):
+    hpt = load_hpt()
+    g = _golden(name)
+    got = _traj(hpt, g["config"], g["nsteps"])
+    for k, rec in enumerate(g["records"]):
+        assert abs(got[k]["C"] - rec["C"]) <= 1e-10, (k, got[k]["C"], rec["C"])
+        assert got[k]["chi_live_max"] == rec["chi_live_max"], (k, got[k]["chi_live_max"], rec["chi_live_max"])
+
+
+@pytest.mark.parametrize("name", ["oracle_4x4_chi40", "oracle_4x4_chi60"])
+def test_saturating_chi_fp32_form(name):
+    # the float32 form (its own cutoff at the float32 noise floor, gauge BP to
+    # its float32 floor 1e-6) against the float64 oracle: the stated 1e-6
+    # bound on |dC| at every recorded layer
+    hpt = load_hpt()
+    g = _golden(name)
+    cfg = dict(g["config"])
+    cfg["bp_tol"] = 1e-6
+    got = _traj(hpt, cfg, g["nsteps"], precision="fp32")
+    d = [abs(got[k]["C"] - rec["C"]) for k, rec in enumerate(g["records"])]
+    print(name, "fp32 form |dC| per layer:", " ".join(f"{x:.1e}" for x in d))
+    assert max(d) <= 1e-6
+
+
 # "bf16x6": the float32 form with its plain products taken as six bf16 MFMA
 # products of split operands (float32-level rounding), held to the same bounds
 @pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
