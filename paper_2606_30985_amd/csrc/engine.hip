@@ -1084,8 +1084,11 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
     // block Jacobi (many workgroups per SVD) when any core is wider than 64,
     // preconditioned: QR of the core, Jacobi on R^T (a graded core needs ~3x
     // fewer sweeps there), then back to the core's singular vectors
-    int nmax = 0;
-    for (auto& j : sj) nmax = std::max(nmax, j.n);
+    int nmax = 0, mmax = 0;
+    for (auto& j : sj) {
+      nmax = std::max(nmax, j.n);
+      mmax = std::max(mmax, j.m);
+    }
     if (nmax > 64) {
       std::vector<QrJob<double>> qj;
       std::vector<SmallGemmJob> back;
@@ -1101,7 +1104,7 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
       }
       QrJob<double>* qd;
       RC(stage(s, qj.data(), nb, &qd));
-      KR(launch_householder<double>(qd, nb, s->stream));
+      KR(launch_householder<double>(qd, nb, s->stream, mmax));
       KR(launch_rcore_precond_prep(cd, nb, s->stream));
       SvdJob* sd;
       RC(stage(s, sj.data(), nb, &sd));

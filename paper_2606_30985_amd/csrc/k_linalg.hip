@@ -290,6 +290,221 @@ __global__ __launch_bounds__(1024) void householder_kernel(const QrJob<T>* jobs)
 }
 
 // ---------------------------------------------------------------------------
+// Blocked Householder QR of one float64 m x n block per workgroup (m <= HBM):
+// the same reflectors, R and explicit Q as householder_kernel, with the work
+// reorganised into panels of HP columns (LAPACK's compact WY form,
+// H_1 ... H_b = I - V T V^T).  A panel is factored in LDS; the trailing
+// columns are then updated 16 at a time, staged through LDS, as
+// C <- C - V T^T (V^T C); Q = H_1 ... H_k is accumulated backwards over the
+// panels with C <- C - V T (V^T C).  Per panel step the sequential part
+// touches only the panel's columns, and the products run on all 1024 threads.
+constexpr int HP = 16;            // panel width
+constexpr int HBM = 512;          // rows held in LDS
+constexpr int HLD = HBM + 1;      // LDS column stride (odd: the 16 columns of a read use distinct banks)
+
+// LDS: Vs, Cs [HLD x HP]; Ts, Ws, Ys [HP x HP]; Wp [4 x HP x HP]
+constexpr size_t HB_LDS = (size_t)(2 * HLD * HP + 3 * HP * HP + 4 * HP * HP) * sizeof(double);
+
+// partial dot products D[a + HP c] = sum_{i < mr} X[i + HLD a] Y[i + HLD c] for
+// a < na, c < nc: four partial sums per entry over rows i = part (mod 4)
+__device__ inline void hb_dots(const double* X, const double* Y, int mr, int na, int nc, double* Wp,
+                               double* D) {
+  const int tid = threadIdx.x, a = tid & 15, c = (tid >> 4) & 15, part = tid >> 8;
+  double acc = 0.0;
+  if (a < na && c < nc)
+    for (int i = part; i < mr; i += 4) acc += X[i + HLD * a] * Y[i + HLD * c];
+  Wp[part * HP * HP + a + HP * c] = acc;
+  __syncthreads();
+  if (tid < HP * HP)
+    D[tid] = (Wp[tid] + Wp[HP * HP + tid]) + (Wp[2 * HP * HP + tid] + Wp[3 * HP * HP + tid]);
+  __syncthreads();
+}
+
+// T (upper triangular, Ts[a + HP b]) of the panel's jb reflectors V (unit
+// lower trapezoidal in Vs): T[b, b] = tau_b, T[a, b] = -tau_b sum_{a <= c < b}
+// T[a, c] (V^T V)[c, b]; each row of T depends only on itself
+__device__ inline void hb_build_T(const double* Vs, int mr, int jb, const double* tau, double* Ts, double* Ys,
+                                  double* Wp) {
+  hb_dots(Vs, Vs, mr, jb, jb, Wp, Ys);
+  if (threadIdx.x < HP) {
+    const int a = threadIdx.x;
+    double row[HP];
+#pragma unroll
+    for (int b = 0; b < HP; ++b) {
+      double v = 0.0;
+      if (a < jb && b < jb) {
+        if (b == a) {
+          v = tau[b];
+        } else if (b > a) {
+          double acc = 0.0;
+#pragma unroll
+          for (int c = 0; c < HP; ++c)
+            if (c >= a && c < b) acc += row[c] * Ys[c + HP * b];
+          v = -tau[b] * acc;
+        }
+      }
+      row[b] = v;
+    }
+#pragma unroll
+    for (int b = 0; b < HP; ++b) Ts[a + HP * b] = row[b];
+  }
+  __syncthreads();
+}
+
+// C (mr x cw in memory at C, leading dimension ldc) <- C - V op(T) (V^T C),
+// op(T) = T^T when trans (applying Q^T), T otherwise (applying Q)
+__device__ inline void hb_apply(double* C, int64_t ldc, int mr, int cw, const double* Vs, const double* Ts,
+                                int jb, bool trans, double* Cs, double* Ws, double* Ys, double* Wp) {
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < mr * cw; idx += blockDim.x) {
+    const int i = idx % mr, c = idx / mr;
+    Cs[i + HLD * c] = C[i + (int64_t)c * ldc];
+  }
+  __syncthreads();
+  hb_dots(Vs, Cs, mr, jb, cw, Wp, Ws);
+  if (tid < HP * HP) {
+    const int a = tid & 15, c = tid >> 4;
+    double v = 0.0;
+    if (a < jb && c < cw) {
+      if (trans)
+        for (int b = 0; b <= a; ++b) v += Ts[b + HP * a] * Ws[b + HP * c];
+      else
+        for (int b = a; b < jb; ++b) v += Ts[a + HP * b] * Ws[b + HP * c];
+    }
+    Ys[a + HP * c] = v;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < mr * cw; idx += blockDim.x) {
+    const int i = idx % mr, c = idx / mr;
+    double v = Cs[i + HLD * c];
+#pragma unroll
+    for (int a = 0; a < HP; ++a)
+      if (a < jb) v -= Vs[i + HLD * a] * Ys[a + HP * c];
+    C[i + (int64_t)c * ldc] = v;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void householder_blocked_kernel(const QrJob<double>* jobs) {
+  const QrJob<double> job = jobs[blockIdx.x];
+  if (gated_out(job.gate, job.gate_zero)) return;
+  const int m = job.m, n = job.n, k = m < n ? m : n;
+  double* A = job.A;
+  const int64_t lda = job.lda;
+  double* tau = job.tau;
+  extern __shared__ double hlds[];
+  double* Vs = hlds;
+  double* Cs = Vs + HLD * HP;
+  double* Ts = Cs + HLD * HP;
+  double* Ws = Ts + HP * HP;
+  double* Ys = Ws + HP * HP;
+  double* Wp = Ys + HP * HP;
+  __shared__ double sh[16];
+  __shared__ double s_beta[1024];   // min(m, n) <= 1024 enforced by the caller
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+
+  for (int j0 = 0; j0 < k; j0 += HP) {
+    const int jb = min(HP, k - j0), mr = m - j0;
+    double* Ap = A + j0 + (int64_t)j0 * lda;
+    for (int idx = tid; idx < mr * jb; idx += blockDim.x) {
+      const int i = idx % mr, c = idx / mr;
+      Vs[i + HLD * c] = Ap[i + (int64_t)c * lda];
+    }
+    __syncthreads();
+    // unblocked factorisation of the panel in LDS
+    for (int jj = 0; jj < jb; ++jj) {
+      // alpha is read before the barriers inside block_sum
+      const double alpha = Vs[jj + HLD * jj];
+      double part = 0.0;
+      for (int i = jj + 1 + tid; i < mr; i += blockDim.x) {
+        const double x = Vs[i + HLD * jj];
+        part += x * x;
+      }
+      const double ss = block_sum(part, sh);
+      double beta, t;
+      if (ss == 0.0) {
+        t = 0.0;
+        beta = alpha;
+      } else {
+        const double sigma = sqrt(alpha * alpha + ss);
+        beta = alpha >= 0.0 ? -sigma : sigma;
+        t = (beta - alpha) / beta;
+        const double scal = 1.0 / (alpha - beta);
+        for (int i = jj + 1 + tid; i < mr; i += blockDim.x) Vs[i + HLD * jj] *= scal;
+      }
+      if (tid == 0) {
+        tau[j0 + jj] = t;
+        s_beta[j0 + jj] = beta;
+      }
+      __syncthreads();
+      if (t != 0.0) {
+        for (int c = jj + 1 + wave; c < jb; c += nw) {
+          double w = 0.0;
+          for (int i = jj + 1 + lane; i < mr; i += 64) w += Vs[i + HLD * jj] * Vs[i + HLD * c];
+          w = (wave_sum(w) + Vs[jj + HLD * c]) * t;
+          for (int i = jj + 1 + lane; i < mr; i += 64) Vs[i + HLD * c] -= Vs[i + HLD * jj] * w;
+          if (lane == 0) Vs[jj + HLD * c] -= w;
+        }
+      }
+      __syncthreads();
+    }
+    // panel back to memory: R above the diagonal, beta on it, v below
+    for (int idx = tid; idx < mr * jb; idx += blockDim.x) {
+      const int i = idx % mr, c = idx / mr;
+      Ap[i + (int64_t)c * lda] = (i == c) ? s_beta[j0 + c] : Vs[i + HLD * c];
+    }
+    __syncthreads();
+    if (j0 + jb >= n) break;
+    // V: unit lower trapezoidal
+    for (int idx = tid; idx < jb * jb; idx += blockDim.x) {
+      const int a = idx % jb, c = idx / jb;
+      if (a <= c) Vs[a + HLD * c] = (a == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    hb_build_T(Vs, mr, jb, tau + j0, Ts, Ys, Wp);
+    for (int c0 = j0 + jb; c0 < n; c0 += HP)
+      hb_apply(A + j0 + (int64_t)c0 * lda, lda, mr, min(HP, n - c0), Vs, Ts, jb, true, Cs, Ws, Ys, Wp);
+  }
+  // R with non-negative diagonal
+  for (int idx = tid; idx < k * n; idx += blockDim.x) {
+    const int i = idx % k, c = idx / k;
+    const double sg = s_beta[i] < 0.0 ? -1.0 : 1.0;
+    double v = 0.0;
+    if (c == i)
+      v = s_beta[i] * sg;
+    else if (c > i)
+      v = A[i + (int64_t)c * lda] * sg;
+    job.R[i + (int64_t)c * job.ldr] = v;
+  }
+  __syncthreads();
+  if (!job.form_q) return;
+  // Q = H_1 ... H_k (m x k), panels from the last: columns >= j0 + jb hold the
+  // product of the later panels (rows < j0 zero), the panel's own columns
+  // start as the identity
+  for (int j0 = ((k - 1) / HP) * HP; j0 >= 0; j0 -= HP) {
+    const int jb = min(HP, k - j0), mr = m - j0;
+    double* Ap = A + j0 + (int64_t)j0 * lda;
+    for (int idx = tid; idx < mr * jb; idx += blockDim.x) {
+      const int i = idx % mr, c = idx / mr;
+      Vs[i + HLD * c] = i < c ? 0.0 : (i == c ? 1.0 : Ap[i + (int64_t)c * lda]);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < m * jb; idx += blockDim.x) {
+      const int i = idx % m, c = idx / m;
+      A[i + (int64_t)(j0 + c) * lda] = (i == j0 + c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    hb_build_T(Vs, mr, jb, tau + j0, Ts, Ys, Wp);
+    for (int c0 = j0; c0 < k; c0 += HP)
+      hb_apply(A + j0 + (int64_t)c0 * lda, lda, mr, min(HP, k - c0), Vs, Ts, jb, false, Cs, Ws, Ys, Wp);
+  }
+  for (int idx = tid; idx < m * k; idx += blockDim.x) {
+    const int i = idx % m, c = idx / m;
+    if (s_beta[c] < 0.0) A[i + (int64_t)c * lda] = -A[i + (int64_t)c * lda];
+  }
+}
+
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const SvdJob* jobs) {
   const SvdJob job = jobs[blockIdx.x];
   const int m = job.m, n = job.n;
@@ -824,88 +1039,84 @@ __global__ void sel_kernel(const SelJob* jobs) {
   }
 }
 
-// Inverse of an upper-triangular R: Y = (R^T)^{-1} is lower triangular and
-// column c of Y follows from forward substitution with the columns of R
-// (contiguous reads); one wave per column, lanes over the inner index.
-// Rinv = Y^T.
-// X = R^-1 of an upper-triangular n x n R (n <= 1024), by block rows from
-// the bottom: X[I, :] = R_II^-1 (E[I, :] - sum_{K > I} R_IK X[K, :]) with
-// 16-row blocks.  Per block row: its rows of R staged in LDS, the 16 x 16
-// inverse of R_II built by 16 threads (one column each), then one thread per
-// column j of X forms the 16 sums over k in (block, j] and the block row.
-// Three barriers per block row instead of a reduction per entry.
-constexpr int TB = 16;
+// X = R^-1 of an upper-triangular n x n R (n <= 1024).  The columns of X are
+// independent, so each workgroup takes one job's block of 16 columns
+// [c0, c1) and forms its rows from the bottom in 16-row blocks:
+// X[I, cols] = R_II^-1 (E[I, cols] - sum_{k >= r1} R[I, k] X[k, cols]).  The
+// column block lives in LDS (rows below c1 are zero).  The block row of R is
+// staged through LDS in chunks of 128 columns, loaded by all threads with 16
+// consecutive rows of one column (128 bytes) per k, so the sums read LDS; the
+// 16 x 16 inverse of R_II comes from back substitution by 16 threads on the
+// staged diagonal block.
+constexpr int TB = 16, TBP = TB + 1, TKC = 128, TKP = TKC + 1;
 
-__global__ __launch_bounds__(1024) void tri_inverse_kernel(const TriInvJob* jobs) {
-  const TriInvJob job = jobs[blockIdx.x];
+__global__ __launch_bounds__(256) void tri_inverse_kernel(const TriInvJob* jobs) {
+  const TriInvJob job = jobs[blockIdx.y];
   if (gated_out(job.gate, job.gate_zero)) return;
   const int n = job.n;
+  const int c0 = blockIdx.x * TB;
+  if (c0 >= n) return;
+  const int c1 = min(n, c0 + TB), cw = c1 - c0;
   const double* R = job.R;
-  double* X = job.Ri;
-  const int64_t ldr = job.ldr, ldi = job.ldri;
-  const int tid = threadIdx.x;
+  const int64_t ldr = job.ldr;
   extern __shared__ double tlds[];
-  double* Rs = tlds;                    // Rs[t * n + k] = R[r0 + t, k], k >= r0
-  double* RI = tlds + TB * n;           // RI[t * (TB + 1) + u] = (R_II^-1)[t, u]
-  for (int idx = tid; idx < n * n; idx += blockDim.x) {
-    const int i = idx % n, c = idx / n;
-    if (i > c) X[i + (int64_t)c * ldi] = 0.0;
-  }
-  const int nb = (n + TB - 1) / TB;
-  for (int I = nb - 1; I >= 0; --I) {
-    const int r0 = I * TB, kw = n - r0 < TB ? n - r0 : TB, r1 = r0 + kw;
-    for (int idx = tid; idx < kw * (n - r0); idx += blockDim.x) {
-      const int t = idx % kw, k = r0 + idx / kw;
-      Rs[t * n + k] = R[r0 + t + (int64_t)k * ldr];
+  double* Rs = tlds;                       // Rs[t * TKP + kk] = R[r0 + t, k0 + kk]
+  double* RI = Rs + TB * TKP;              // RI[t * TBP + q] = (R_II^-1)[t, q]
+  double* E = RI + TB * TBP;               // E[t * TBP + u]: right-hand sides of the block row
+  double* Xs = E + TB * TBP;               // Xs[k * TB + u] = X[k, c0 + u], k < c1
+  const int tid = threadIdx.x, t = tid & 15, u = tid >> 4;
+  auto stage_rows = [&](int r0, int kw, int k0, int kc) {
+    for (int idx = tid; idx < TB * kc; idx += blockDim.x) {
+      const int tt = idx & 15, kk = idx >> 4;
+      Rs[tt * TKP + kk] = tt < kw ? R[r0 + tt + (int64_t)(k0 + kk) * ldr] : 0.0;
     }
+  };
+  for (int I = (c1 - 1) / TB; I >= 0; --I) {
+    const int r0 = I * TB, kw = min(TB, n - r0), r1 = r0 + kw;
+    // diagonal block
+    stage_rows(r0, kw, r0, kw);
     __syncthreads();
     if (tid < kw) {
-      // column u = tid of R_II^-1: back substitution on R_II y = e_u
-      const int u = tid;
+      // column v of R_II^-1: back substitution on R_II y = e_v
+      const int v = tid;
       double y[TB];
 #pragma unroll
-      for (int t = TB - 1; t >= 0; --t) {
-        double v = 0.0;
-        if (t <= u) {
-          double acc = (t == u) ? 1.0 : 0.0;
+      for (int a = TB - 1; a >= 0; --a) {
+        double val = 0.0;
+        if (a <= v) {
+          double acc = (a == v) ? 1.0 : 0.0;
 #pragma unroll
-          for (int q = t + 1; q < TB; ++q)
-            if (q <= u) acc -= Rs[t * n + r0 + q] * y[q];
-          v = acc / Rs[t * n + r0 + t];
+          for (int q = a + 1; q < TB; ++q)
+            if (q <= v) acc -= Rs[a * TKP + q] * y[q];
+          val = acc / Rs[a * TKP + a];
         }
-        y[t] = v;
+        y[a] = val;
       }
 #pragma unroll
-      for (int t = 0; t < TB; ++t)
-        if (t < kw) RI[t * (TB + 1) + u] = y[t];
+      for (int a = 0; a < TB; ++a)
+        if (a < kw) RI[a * TBP + v] = y[a];
+    }
+    double sacc = 0.0;
+    for (int k0 = r1; k0 < c1; k0 += TKC) {
+      const int kc = min(TKC, c1 - k0);
+      __syncthreads();   // previous readers of Rs are done
+      stage_rows(r0, kw, k0, kc);
+      __syncthreads();
+      if (t < kw && u < cw)
+        for (int kk = 0; kk < kc; ++kk) sacc += Rs[t * TKP + kk] * Xs[(k0 + kk) * TB + u];
+    }
+    E[t * TBP + u] = ((r0 + t == c0 + u) ? 1.0 : 0.0) - sacc;
+    __syncthreads();
+    if (t < kw && u < cw) {
+      double val = 0.0;
+      for (int q = t; q < kw; ++q) val += RI[t * TBP + q] * E[q * TBP + u];
+      Xs[(r0 + t) * TB + u] = val;
     }
     __syncthreads();
-    for (int j = r0 + tid; j < n; j += blockDim.x) {
-      double S[TB];
-#pragma unroll
-      for (int t = 0; t < TB; ++t) S[t] = 0.0;
-      // S[t] = sum over k in [r1, j] of R[r0 + t, k] X[k, j]
-      for (int k = r1; k <= j; ++k) {
-        const double x = X[k + (int64_t)j * ldi];
-#pragma unroll
-        for (int t = 0; t < TB; ++t)
-          if (t < kw) S[t] += Rs[t * n + k] * x;
-      }
-      double e[TB];
-#pragma unroll
-      for (int u = 0; u < TB; ++u) e[u] = (r0 + u == j ? 1.0 : 0.0) - S[u];
-#pragma unroll
-      for (int t = 0; t < TB; ++t) {
-        if (t < kw && r0 + t <= j) {
-          double v = 0.0;
-#pragma unroll
-          for (int u = 0; u < TB; ++u)
-            if (u >= t && u < kw) v += RI[t * (TB + 1) + u] * e[u];
-          X[r0 + t + (int64_t)j * ldi] = v;
-        }
-      }
-    }
-    __syncthreads();
+  }
+  for (int idx = tid; idx < n * cw; idx += blockDim.x) {
+    const int i = idx % n, c = idx / n;
+    job.Ri[i + (int64_t)(c0 + c) * job.ldri] = i < c1 ? Xs[i * TB + c] : 0.0;
   }
 }
 
@@ -987,14 +1198,20 @@ int launch_pseudo_sqrt(const PsqJob* jobs, int njobs, double eps_pinv, hipStream
 }
 
 template <typename T>
-int launch_householder(const QrJob<T>* jobs, int njobs, hipStream_t s) {
+int launch_householder(const QrJob<T>* jobs, int njobs, hipStream_t s, int mmax) {
   if (njobs <= 0) return 0;
+  if (sizeof(T) == 8 && mmax >= 1 && mmax <= HBM) {
+    hipLaunchKernelGGL(householder_blocked_kernel, dim3(njobs), dim3(1024), HB_LDS, s,
+                       (const QrJob<double>*)jobs);
+    HPT_LAUNCH_CHECK("householder_blocked_kernel");
+    return 0;
+  }
   hipLaunchKernelGGL(householder_kernel<T>, dim3(njobs), dim3(1024), 0, s, jobs);
   HPT_LAUNCH_CHECK("householder_kernel");
   return 0;
 }
-template int launch_householder<double>(const QrJob<double>*, int, hipStream_t);
-template int launch_householder<float>(const QrJob<float>*, int, hipStream_t);
+template int launch_householder<double>(const QrJob<double>*, int, hipStream_t, int);
+template int launch_householder<float>(const QrJob<float>*, int, hipStream_t, int);
 
 int launch_jacobi_svd(const SvdJob* jobs, int njobs, hipStream_t s) {
   if (njobs <= 0) return 0;
@@ -1096,8 +1313,8 @@ int launch_cholesky(const CholJob* jobs, int njobs, double rel_tol, hipStream_t 
 
 int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s, int nmax) {
   if (njobs <= 0) return 0;
-  if (nmax < 1 || nmax > 1024) return -1;
-  const size_t lds = (size_t)(TB * nmax + TB * (TB + 1)) * sizeof(double);
+  if (nmax < 1 || nmax > 1024 || njobs > 65535) return -1;
+  const size_t lds = (size_t)(TB * TKP + 2 * TB * TBP + TB * nmax) * sizeof(double);
   static int max_lds = 0;
   if (!max_lds) {
     int dev = 0;
@@ -1105,7 +1322,7 @@ int launch_tri_inverse(const TriInvJob* jobs, int njobs, hipStream_t s, int nmax
     HPT_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   }
   if (lds > (size_t)max_lds) return -1;
-  hipLaunchKernelGGL(tri_inverse_kernel, dim3(njobs), dim3(1024), lds, s, jobs);
+  hipLaunchKernelGGL(tri_inverse_kernel, dim3((nmax + TB - 1) / TB, njobs), dim3(256), lds, s, jobs);
   HPT_LAUNCH_CHECK("tri_inverse_kernel");
   return 0;
 }

@@ -106,7 +106,9 @@ struct SmallGemmJob {
 
 int launch_pseudo_sqrt(const PsqJob* jobs, int njobs, double eps_pinv, hipStream_t s);
 template <typename T>
-int launch_householder(const QrJob<T>* jobs, int njobs, hipStream_t s);
+// mmax: largest m of the jobs when known on the host (float64 blocks of up to
+// 512 rows take the blocked kernel); 0 for the unblocked kernel
+int launch_householder(const QrJob<T>* jobs, int njobs, hipStream_t s, int mmax = 0);
 int launch_jacobi_svd(const SvdJob* jobs, int njobs, hipStream_t s);
 // Block one-sided Jacobi: every launch of a round pairs column blocks of all
 // jobs, one workgroup per block pair with the block columns in LDS.  Needs
