@@ -701,6 +701,80 @@ __global__ __launch_bounds__(256) void mode_product_kernel(const float* __restri
   }
 }
 
+// The same product in 32-row strips for even inner: lane (r16, kq) reads rows
+// 2 r16 and 2 r16 + 1 of the strip as one float2 per k and feeds them to two
+// MFMAs that share the factor operand, so block h of the result holds rows
+// 2 r16 + h and the float2 stores of 16 lanes cover 128 contiguous bytes of a
+// column (the 16-row form moves 64-byte pieces); half the load and factor
+// read instructions per MFMA.  Every output element sees the same MFMA
+// operands in the same k order as in the 16-row form.
+template <int NP, int KS>
+__global__ __launch_bounds__(256) void mode_product32_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                                             const float* __restrict__ S, int n, int64_t inner,
+                                                             int64_t Z, int64_t strips_per_z) {
+  constexpr int NB = NP / 16;
+  constexpr int SP = NP + ((NP % 32) == 0 ? 16 : 0);   // row stride = 16 mod 32
+  __shared__ float Sl[NP * SP];                         // Sl[k * SP + j] = S[j, k]
+  for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
+    const int j = idx % NP, k = idx / NP;
+    Sl[k * SP + j] = (j < n && k < n) ? S[j + (int64_t)k * n] : 0.f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int64_t total = strips_per_z * Z;
+  float2 y[KS];
+  // rows past the end read the clamped, in-range pair inner - 2, inner - 1
+  // (never stored); k >= n read k = n - 1 (the factor's rows k >= n are zero)
+  auto fetch = [&](int64_t st, float2* v) {
+    const int64_t z = st / strips_per_z;
+    const int64_t r = (st % strips_per_z) * 32 + 2 * r16;
+    const uint32_t row = (uint32_t)(r < inner ? r : inner - 2);
+    const char* base = (const char*)(src + z * inner * n);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const uint32_t k = (uint32_t)min(ks * 4 + kq, n - 1);
+      v[ks] = *(const float2*)(base + (row + k * (uint32_t)inner) * 4u);
+    }
+  };
+  // no prefetch of the next strip (it would not fit the registers): a strip is
+  // 350 MFMAs per wave, and the other waves of the SIMD cover its load latency
+  int64_t st = blockIdx.x * (int64_t)(blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (; st < total; st += nwaves) {
+    fetch(st, y);
+    f4 acc0[NB], acc1[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      acc0[cb] = f4{0.f, 0.f, 0.f, 0.f};
+      acc1[cb] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+    int opq = 0;  // keeps the factor reads inside the strip loop
+    asm volatile("" : "+v"(opq));
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const float* Sk = Sl + opq + (ks * 4 + kq) * SP + r16;
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) {
+        const float a = Sk[cb * 16];
+        acc0[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, y[ks].x, acc0[cb], 0, 0, 0);
+        acc1[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, y[ks].y, acc1[cb], 0, 0, 0);
+      }
+    }
+    const int64_t z = st / strips_per_z;
+    const int64_t row = (st % strips_per_z) * 32 + 2 * r16;
+    if (row < inner) {
+      float* Cz = dst + z * inner * n + row;
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int col = cb * 16 + 4 * kq + e;
+          if (col < n) *(float2*)(Cz + (int64_t)col * inner) = make_float2(acc0[cb][e], acc1[cb][e]);
+        }
+    }
+  }
+}
+
 // dst[j, b] = sum_k S[j, k] src[k, b]; src, dst n x outer (the leading leg).
 // Each lane reads 4 consecutive k of one column (one 16-byte load when
 // n % 4 == 0); the MFMA's reduction index is permuted accordingly (lane
@@ -1264,9 +1338,16 @@ int launch_mode(const float* src, float* dst, const float* S, int n, int64_t inn
       hipLaunchKernelGGL((mode_product_lead_kernel<NP, false>), dim3(g), dim3(256), 0, s, src, dst, S, n, outer);
     }
   } else {
-    const int64_t spz = ceil_div(inner, 16);
-    const int g = resident_grid((const void*)mode_product_kernel<NP, KS>, 256, spz * outer);
-    hipLaunchKernelGGL((mode_product_kernel<NP, KS>), dim3(g), dim3(256), 0, s, src, dst, S, n, inner, outer, spz);
+    if (inner % 2 == 0 && inner >= 32) {
+      const int64_t spz = ceil_div(inner, 32);
+      const int g = resident_grid((const void*)mode_product32_kernel<NP, KS>, 256, spz * outer);
+      hipLaunchKernelGGL((mode_product32_kernel<NP, KS>), dim3(g), dim3(256), 0, s, src, dst, S, n, inner, outer,
+                         spz);
+    } else {
+      const int64_t spz = ceil_div(inner, 16);
+      const int g = resident_grid((const void*)mode_product_kernel<NP, KS>, 256, spz * outer);
+      hipLaunchKernelGGL((mode_product_kernel<NP, KS>), dim3(g), dim3(256), 0, s, src, dst, S, n, inner, outer, spz);
+    }
   }
   HPT_LAUNCH_CHECK("mode_product_kernel");
   return 0;

@@ -1260,6 +1260,8 @@ int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, h
   const size_t budget = (size_t)max_lds > 2048 ? (size_t)max_lds - 2048 : 0;
   int w = 16;
   while (w > 2 && (size_t)(2 * w * mmax + 4 * w * w) * 8 > budget) w /= 2;
+  // one wave per column pair of a sub-round (w pairs over the 2w columns)
+  const int bj_threads = 64 * std::max(4, std::min(16, w));
   const size_t lds = (size_t)(2 * w * mmax + 4 * w * w) * 8;
   if (lds > budget || njobs > 65535) return -1;
   const int nb = (nmax + w - 1) / w, nb2 = nb + (nb & 1);
@@ -1272,7 +1274,7 @@ int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, h
     hipLaunchKernelGGL(bj_sweep_begin_kernel, dim3(njobs), dim3(64), 0, s, jobs, sweep);
     HPT_LAUNCH_CHECK("bj_sweep_begin_kernel");
     for (int r = 0; r < nb2 - 1; ++r) {
-      hipLaunchKernelGGL(bj_round_kernel, dim3(std::max(1, nb2 / 2), njobs), dim3(1024), lds, s, jobs, r,
+      hipLaunchKernelGGL(bj_round_kernel, dim3(std::max(1, nb2 / 2), njobs), dim3(bj_threads), lds, s, jobs, r,
                          sweep, w);
       HPT_LAUNCH_CHECK("bj_round_kernel");
     }
@@ -1289,7 +1291,7 @@ int launch_block_jacobi_svd(const SvdJob* jobs, const SvdJob* host, int njobs, h
       ++sweep;   // that sweep has begun: run its rounds next
       last = sweep;
       for (int r = 0; r < nb2 - 1; ++r) {
-        hipLaunchKernelGGL(bj_round_kernel, dim3(std::max(1, nb2 / 2), njobs), dim3(1024), lds, s, jobs, r,
+        hipLaunchKernelGGL(bj_round_kernel, dim3(std::max(1, nb2 / 2), njobs), dim3(bj_threads), lds, s, jobs, r,
                            sweep, w);
         HPT_LAUNCH_CHECK("bj_round_kernel");
       }
