@@ -34,9 +34,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
 FORM_NAMES = {"fp32": "FP32-MFMA form", "bf16x6": "FP32 form with split-bf16 (x6) GEMMs", "fp64": "FP64 plain form"}
-KERNEL_NAMES = {"gemm": "tile_gemm_kernel<float> / gemm_pipe_kernel (tiled MFMA GEMM)",
+KERNEL_NAMES = {"gemm": "gemm_f32_kernel / gemm_pipe_kernel (tiled MFMA GEMM)",
                 "gram64": "gram64_kernel (float64-accumulated Gram, MFMA f64)",
-                "mode": "mode_product_kernel (MFMA mode product, factor in LDS)",
+                "mode": "mode_product32_kernel / mode_product_kernel (MFMA mode product, factor in LDS)",
                 "leggram": "leg_gram_kernel (MFMA leg Gram of the gauge BP, with its partial sum)",
                 "bsplit": "tile_gemm_kernel<split> (six bf16 MFMA products of split float32 operands)"}
 
@@ -71,6 +71,12 @@ def parse():
                     help="large: the 10x10 chi=100 run (default); batched: the independent-runs set; "
                          "learned: the learned warm start of the measurement BP; permute: device permutations")
     ap.add_argument("--learn-steps", type=int, default=3000)
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="no run: summarise a rocprofv3 --kernel-trace csv of a --trace-markers run "
+                         "(kernel time between the two marker kernels) and exit")
+    ap.add_argument("--summarize-pmc", metavar="DIR",
+                    help="no run: sum a rocprofv3 --pmc csv of a --profile-all --calibrate-copy run per kernel "
+                         "family (the first permute_generic dispatch is the calibration copy) and exit")
     ap.add_argument("--batch-runs", type=int, default=64)
     ap.add_argument("--batch-chi", type=int, default=40)
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -492,8 +498,88 @@ def chi_stats(sim):
     return chis, {"min": min(chis), "mean": sum(chis) / len(chis), "max": max(chis)}
 
 
+def _csv_in(d, suffix):
+    import glob
+    fs = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not fs:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return fs[0]
+
+
+def summarize_trace(d):
+    """Kernel time between the two marker kernels (the only dispatches not
+    from this library) of a --trace-markers run: the timed layers."""
+    import csv
+    import collections
+    rows = list(csv.DictReader(open(_csv_in(d, "kernel_trace.csv"))))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    mk = [i for i, r in enumerate(rows) if "hpt::" not in r["Kernel_Name"] and "rocclr" not in r["Kernel_Name"]]
+    if len(mk) < 2:
+        raise SystemExit("no marker kernels in the trace (run bench.py with --trace-markers)")
+    a, b = mk[0], mk[-1]
+    win = rows[a + 1:b]
+    t0, t1 = int(rows[a]["End_Timestamp"]), int(rows[b]["Start_Timestamp"])
+    tot = collections.defaultdict(lambda: [0, 0])
+    busy = 0
+    for r in win:
+        dt = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        k = r["Kernel_Name"].replace("hpt::(anonymous namespace)::", "")
+        tot[k][0] += 1
+        tot[k][1] += dt
+        busy += dt
+    print(f"window: {len(win)} dispatches between the markers, {(t1 - t0) / 1e9:.3f} s wall, "
+          f"kernel busy {busy / 1e9:.3f} s")
+    print("  share   calls   total_ms     avg_us  kernel")
+    for k, (n, t) in sorted(tot.items(), key=lambda x: -x[1][1])[:40]:
+        print(f"{100 * t / busy:6.2f}% {n:7d} {t / 1e6:10.2f} {t / n / 1e3:10.1f}  {k[:130]}")
+    print("per kernel family (the contraction kinds of the bench line):")
+    for name, pats in PMC_FAMILIES.items():
+        n = t = 0
+        for k, (c, dt) in tot.items():
+            if any(p in k for p in pats) and not (name == "mode" and "f64acc" in k):
+                n += c
+                t += dt
+        if n:
+            print(f"  {name}: {n} dispatches, {t / 1e6:.2f} ms, average {t / n / 1e3:.1f} us")
+
+
+PMC_FAMILIES = {"mode_f64acc": ("mode_product_f64acc",), "mode": ("mode_product",), "gram64": ("gram64_kernel",),
+                "leggram": ("leg_gram",), "gemm": ("gemm_f32_kernel", "gemm_pipe_kernel", "tile_gemm_kernel"),
+                "last_leg": ("last_leg_kernel",)}
+
+
+def summarize_pmc(d):
+    """Per kernel family and counter: dispatches and the counter summed over
+    them (KiB, as rocprofv3 reports FETCH_SIZE / WRITE_SIZE), with the value of
+    the calibration copy (first permute_generic dispatch, --calibrate-copy)."""
+    import csv
+    import collections
+    rows = sorted(csv.DictReader(open(_csv_in(d, "counter_collection.csv"))), key=lambda r: int(r["Dispatch_Id"]))
+    tot = collections.defaultdict(float)
+    cnt = collections.Counter()
+    calib = {}
+    for r in rows:
+        k, c, v = r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])
+        if "permute_generic" in k:
+            calib.setdefault(c, v)
+            continue
+        for name, pats in PMC_FAMILIES.items():
+            if any(p in k for p in pats):
+                tot[(name, c)] += v
+                cnt[(name, c)] += 1
+                break
+    for c, v in calib.items():
+        print(f"{c} calibration_copy {v:.6g}")
+    for (name, c), v in sorted(tot.items()):
+        print(f"{c} {name} dispatches {cnt[(name, c)]} sum {v:.6e}")
+
+
 def main():
     args = parse()
+    if args.summarize_trace:
+        return summarize_trace(args.summarize_trace)
+    if args.summarize_pmc:
+        return summarize_pmc(args.summarize_pmc)
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU: the lattice of one run fits one MI355X "
                                    "(multi-GPU sharding is a design note only); run with --gpus 1"}))
