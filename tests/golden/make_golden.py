@@ -35,6 +35,49 @@ CASES = {
 }
 
 BOND_CASES = ("oracle_bond_4x4_chi100",)
+BP_CASES = ("oracle_bp_4x4_chi100",)
+BP_SAMPLES = 64
+
+
+def bp_case(name):
+    """Belief propagation at chi = 100 on the seeded saturated state of
+    tests/fullsize_case.py: one gauge-BP sweep (damping 0.5) from the seeded
+    environment messages, and three measurement-BP sweeps from the uniform
+    start (tolerance never met, so all three run).  For every chi = 100 bond
+    and direction: the diagonal, sampled off-diagonal entries and the
+    Frobenius norm of the new gauge message; every measurement message whole,
+    and C at the messages of the third sweep."""
+    import dataclasses
+    import numpy as np
+    from tests import fullsize_case as fc
+    t0 = time.time()
+    net, _ = fc.state()
+    net.cfg = dataclasses.replace(net.cfg, bp_max_sweeps=1, bp_init="warm", meas_max_sweeps=3, meas_tol=1e-300)
+    print(f"state {time.time() - t0:.1f}s", flush=True)
+    sweeps, delta = net.gauge_bp()
+    print(f"gauge sweep {time.time() - t0:.1f}s", flush=True)
+    rng = np.random.default_rng(1)
+    gauge = []
+    for b in range(net.lat.n_bonds):
+        if net.chi[b] != fc.CFG["chi_max"]:
+            continue
+        for d in range(2):
+            M = net.M[b][d]
+            c = M.shape[0]
+            i = rng.integers(0, c, BP_SAMPLES)
+            j = rng.integers(0, c, BP_SAMPLES)
+            gauge.append(dict(bond=b, dir=d, diag=[float(x) for x in np.diag(M)], i=[int(x) for x in i],
+                              j=[int(x) for x in j], val=[float(M[a, bb]) for a, bb in zip(i, j)],
+                              fro=float(np.linalg.norm(M))))
+    r = net.measure()
+    print(f"measurement sweeps {time.time() - t0:.1f}s", flush=True)
+    meas = [dict(bond=b, dir=d, m=[float(x) for x in net.meas_messages[b][d]])
+            for b in range(net.lat.n_bonds) for d in range(2)]
+    out = dict(config=fc.CFG, seed=fc.SEED, source="oracle/ (CPU FP64 restatement of the method)",
+               gauge_delta=float(delta), gauge=gauge, meas=meas, meas_sweeps=int(r["meas_sweeps"]),
+               meas_delta=float(r["meas_delta"]), C=float(r["C"]))
+    with open(os.path.join(HERE, name + ".json"), "w") as f:
+        json.dump(out, f)
 
 
 def bond_case(name):
@@ -69,6 +112,8 @@ def bond_case(name):
 def main(name):
     if name in BOND_CASES:
         return bond_case(name)
+    if name in BP_CASES:
+        return bp_case(name)
     cfg, n = CASES[name]
     t0 = time.time()
 
