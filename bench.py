@@ -545,33 +545,39 @@ def summarize_trace(d):
 
 PMC_FAMILIES = {"mode_f64acc": ("mode_product_f64acc",), "mode": ("mode_product",), "gram64": ("gram64_kernel",),
                 "leggram": ("leg_gram",), "gemm": ("gemm_f32_kernel", "gemm_pipe_kernel", "tile_gemm_kernel"),
-                "last_leg": ("last_leg_kernel",)}
+                "last_leg": ("last_leg_kernel",), "permute": ("swap_", "permute_generic")}
 
 
 def summarize_pmc(d):
-    """Per kernel family and counter: dispatches and the counter summed over
-    them (KiB, as rocprofv3 reports FETCH_SIZE / WRITE_SIZE), with the value of
-    the calibration copy (first permute_generic dispatch, --calibrate-copy)."""
+    """Per kernel family, per kernel and counter: dispatches and the counter
+    summed over them (KiB, as rocprofv3 reports FETCH_SIZE / WRITE_SIZE).  A
+    permute_generic dispatch that is the run's first dispatch is the
+    calibration copy of --calibrate-copy and is reported apart."""
     import csv
     import collections
     rows = sorted(csv.DictReader(open(_csv_in(d, "counter_collection.csv"))), key=lambda r: int(r["Dispatch_Id"]))
+    first = rows[0]["Dispatch_Id"] if rows else None
     tot = collections.defaultdict(float)
     cnt = collections.Counter()
-    calib = {}
+    per = collections.defaultdict(float)
+    pcnt = collections.Counter()
     for r in rows:
         k, c, v = r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])
-        if "permute_generic" in k:
-            calib.setdefault(c, v)
+        if r["Dispatch_Id"] == first and "permute_generic" in k:
+            print(f"{c} calibration_copy {v:.6g}")
             continue
+        short = k.split("(")[0].replace("hpt::(anonymous namespace)::", "").replace("void ", "")
+        per[(short, c)] += v
+        pcnt[(short, c)] += 1
         for name, pats in PMC_FAMILIES.items():
             if any(p in k for p in pats):
                 tot[(name, c)] += v
                 cnt[(name, c)] += 1
                 break
-    for c, v in calib.items():
-        print(f"{c} calibration_copy {v:.6g}")
     for (name, c), v in sorted(tot.items()):
         print(f"{c} {name} dispatches {cnt[(name, c)]} sum {v:.6e}")
+    for (name, c), v in sorted(per.items()):
+        print(f"{c} kernel {name} dispatches {pcnt[(name, c)]} sum {v:.6e}")
 
 
 def main():
