@@ -566,7 +566,7 @@ def summarize_pmc(d):
         if r["Dispatch_Id"] == first and "permute_generic" in k:
             print(f"{c} calibration_copy {v:.6g}")
             continue
-        short = k.split("(")[0].replace("hpt::(anonymous namespace)::", "").replace("void ", "")
+        short = k.replace("hpt::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
         per[(short, c)] += v
         pcnt[(short, c)] += 1
         for name, pats in PMC_FAMILIES.items():
