@@ -67,9 +67,10 @@ def parse():
     ap.add_argument("--trace", default="", help="append per-step records (JSON lines) to this file")
     ap.add_argument("--profile-all", action="store_true",
                     help="kernel event profile over every layer (warm-up included), for counter comparisons")
-    ap.add_argument("--workload", default="large", choices=["large", "batched", "learned", "permute"],
+    ap.add_argument("--workload", default="large", choices=["large", "batched", "learned", "permute", "damping"],
                     help="large: the 10x10 chi=100 run (default); batched: the independent-runs set; "
-                         "learned: the learned warm start of the measurement BP; permute: device permutations")
+                         "learned: the learned warm start of the measurement BP; permute: device permutations; "
+                         "damping: the measurement-BP damping study on the 4x4 lattice")
     ap.add_argument("--learn-steps", type=int, default=3000)
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="no run: summarise a rocprofv3 --kernel-trace csv of a --trace-markers run "
@@ -314,37 +315,87 @@ def permutes(args):
     print(json.dumps(out), flush=True)
 
 
+def damping(args):
+    """The update-rule experiment of Sec. "BP Fixed-Point Multiplicity": the
+    even 4x4 lattice (several BP fixed points), chi_max = 80, dt = 0.05, to
+    t = 1.9 (38 layers), the measurement BP damped with alpha in {0.5, 0.8,
+    1.0} (1.0 = undamped), tolerance 1e-5 and 100 sweeps as in the paper's
+    runs, no remediation; the gauge BP as in the benchmark.  The state does
+    not depend on the measurement damping, so the three runs evolve the same
+    operator and differ only in which fixed point each measurement finds.
+    Per layer: C, sweeps, final delta; the trap scan of each run."""
+    import torch
+    from paper_2606_30985_amd import hpt, traps
+    cfg = dict(Lx=4, Ly=4, chi_max=80, dt=0.05, J=1.0, h=1.0, bp_tol=1e-5, bp_max_sweeps=100, bp_init="warm",
+               meas_tol=1e-5, meas_max_sweeps=100, trap_retry=0, precision=args.precision)
+    runs = {}
+    t_all = time.perf_counter()
+    for alpha in (0.5, 0.8, 1.0):
+        sim = hpt.Simulator(meas_alpha=alpha, **cfg)
+        recs = [sim.measure()]
+        for _ in range(38):
+            sim.step(1)
+            recs.append(sim.measure())
+            r = recs[-1]
+            print(f"# alpha {alpha} step {r['step']} t={r['step'] * 0.05:.2f} C={r['C']:.6f} "
+                  f"sweeps={r['meas_sweeps']} delta={r['meas_delta']:.1e} gate_err={r['gate_err']:.1e}",
+                  file=sys.stderr, flush=True)
+        sim.close()
+        del sim
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        scan = traps.detect_traps(recs, tol=cfg["meas_tol"], trap_sweeps=30)
+        runs[str(alpha)] = {"C": [r["C"] for r in recs], "sweeps": [r["meas_sweeps"] for r in recs],
+                            "delta": [r["meas_delta"] for r in recs], "gate_err": [r["gate_err"] for r in recs],
+                            "traps": scan}
+    wall = time.perf_counter() - t_all
+    layers = 3 * 38
+    out = {"metric": "measurement-BP damping study (C(t), sweeps and traps per damping)", "value": layers / wall,
+           "unit": "layers/s (all three runs)", "n_gpus": 1, "steps": 38, "warmup": 0,
+           "ms_per_step": 1000.0 * wall / layers, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32" if args.precision != "fp64" else "f64",
+           "data": "synthetic (deterministic initial operator Z_c, no dataset)",
+           "config": {"workload": "4x4 TFIM Heisenberg Z_c(t), chi_max=80, dt=0.05, 38 layers, measurement BP "
+                                  "alpha in {0.5, 0.8, 1.0}, tol 1e-5, 100 sweeps, no remediation",
+                      "runs": runs}}
+    print(json.dumps(out), flush=True)
+
+
 def learned(args):
     """The learned warm start of the measurement BP: training data from runs
-    of the method (4x4 at chi 20/40 and batched-form lattices 3x3..6x6 at chi
-    40, fields away from the held-out ones), the network trained on the GPU
-    by the library's forward/backward/Adam kernels, then 6x6 chi=40 runs at
-    held-out fields, each layer measured twice on identical states (uniform
-    start and learned start).  Reports sweeps to the 1e-10 residual, |dC|
+    of the method (4x4 at chi 20/40 and 5x5 at chi 40, 30 layers each, fields
+    away from the held-out ones), the network trained on the GPU by the
+    library's forward/backward/Adam kernels, then 6x6 chi=40 runs (40 layers)
+    at two held-out fields, each layer measured twice on identical states
+    (uniform start and learned start).  Reports sweeps to the 1e-10 residual, |dC|
     between the two starts, and the trap rate of each (a layer whose C falls
     below half of the previous layer's while its gate error grows less than
-    twofold; the paper's trap rule)."""
+    twofold after a converged BP of at least 30 sweeps; the paper's trap
+    rule, paper_2606_30985_amd.traps)."""
     import numpy as np
     import torch
-    from paper_2606_30985_amd import hpt, inputs
-    common = dict(J=1.0, dt=0.05, bp_tol=1e-10, bp_alpha=0.5, meas_tol=1e-10, meas_max_sweeps=400,
+    from paper_2606_30985_amd import hpt, inputs, traps
+    common = dict(J=1.0, dt=0.05, bp_tol=1e-8, bp_alpha=0.5, bp_init="warm", meas_tol=1e-10, meas_max_sweeps=400,
                   precision=args.precision if args.precision != "bf16x6" else "fp32")
     train_h = [0.5, 0.9, 1.3, 1.7, 2.1, 2.5, 2.9]
     runs = [dict(common, Lx=4, Ly=4, chi_max=20, h=h) for h in train_h[::2]]
     runs += [dict(common, Lx=4, Ly=4, chi_max=40, h=h) for h in train_h[1::2]]
-    runs += [dict(common, Lx=L, Ly=L, chi_max=40, h=h) for L, h in ((5, 0.7), (6, 1.5), (5, 2.3), (6, 2.7))]
-    held = [0.75, 1.25, 2.0, 2.75]
+    runs += [dict(common, Lx=5, Ly=5, chi_max=40, h=h) for h in (0.7, 2.3)]
+    held = [1.25, 2.0]
     t0 = time.perf_counter()
     Xs, Ts = [], []
     for cfg in runs:
         sim = hpt.Simulator(**cfg)
         sim.measure()
-        for _ in range(40):
+        for k in range(30):
             sim.step(1)
             X, base = sim.meas_features()
             sim.measure()
             Xs.append(X)
             Ts.append(sim.meas_targets(base))
+            if k % 10 == 9:
+                print(f"# data run {cfg['Lx']}x{cfg['Ly']} chi {cfg['chi_max']} h {cfg['h']}: layer {k + 1} "
+                      f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
         sim.close()
         print(f"# data: {cfg['Lx']}x{cfg['Ly']} chi {cfg['chi_max']} h {cfg['h']}: {sum(x.shape[0] for x in Xs)} rows "
               f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
@@ -377,24 +428,23 @@ def learned(args):
         uni = hpt.Simulator(**cfg)
         lrn = hpt.Simulator(meas_init="learned", **cfg)
         lrn.set_meas_model(P)
-        su, sl, dc, cu, cl, ge = [], [], [], [], [], []
-        for _ in range(40):
+        su, sl, dc, ru, rl = [], [], [], [uni.measure()], [lrn.measure()]
+        for k in range(40):
             uni.step(1)
             lrn.step(1)
             mu, ml = uni.measure(), lrn.measure()
+            print(f"# held-out h={h} layer {k + 1}: sweeps uniform {mu['meas_sweeps']} learned {ml['meas_sweeps']} "
+                  f"C {mu['C']:.6f} / {ml['C']:.6f}", file=sys.stderr, flush=True)
             su.append(mu["meas_sweeps"])
             sl.append(ml["meas_sweeps"])
             dc.append(abs(mu["C"] - ml["C"]))
-            cu.append(mu["C"])
-            cl.append(ml["C"])
-            ge.append(mu["gate_err"])
-
-        def traps(C):
-            return sum(1 for k in range(1, len(C)) if abs(C[k]) < 0.5 * abs(C[k - 1]) and
-                       (ge[k] < 2 * ge[k - 1] or ge[k] == 0.0))
+            ru.append(mu)
+            rl.append(ml)
         report.append({"h": h, "sweeps_uniform": su, "sweeps_learned": sl,
                        "mean_sweeps_uniform": sum(su) / len(su), "mean_sweeps_learned": sum(sl) / len(sl),
-                       "max_abs_dC": max(dc), "traps_uniform": traps(cu), "traps_learned": traps(cl)})
+                       "max_abs_dC": max(dc),
+                       "traps_uniform": traps.detect_traps(ru, tol=common["meas_tol"])["type1"],
+                       "traps_learned": traps.detect_traps(rl, tol=common["meas_tol"])["type1"]})
         print(f"# held-out h={h}: sweeps uniform {sum(su) / len(su):.1f} learned {sum(sl) / len(sl):.1f} "
               f"max|dC| {max(dc):.1e}", file=sys.stderr, flush=True)
         uni.close()
@@ -407,8 +457,8 @@ def learned(args):
            "vs_baseline": None, "dtype": "bf16 weights, f32 accumulation",
            "data": "synthetic (BP fixed points generated by the method's own runs)",
            "config": {"workload": "6x6 TFIM, chi_max=40, dt=0.05, 40 layers, held-out h "
-                                  f"{held}; training runs 4x4 chi 20/40 and 5x5/6x6 chi 40 at h {train_h} and "
-                                  "0.7/1.5/2.3/2.7; edge-wise MLP 16 -> 128 (tanh) -> 1",
+                                  f"{held}; training runs 4x4 chi 20/40 at h {train_h} and 5x5 chi 40 at h "
+                                  "0.7/2.3 (30 layers each); edge-wise MLP 16 -> 128 (tanh) -> 1",
                       "training_rows": int(X.shape[0]), "data_seconds": t_data, "train_seconds": t_train,
                       "loss_curve": losses, "loss_of_zero_correction": zero,
                       "mean_sweeps_uniform": mu_, "mean_sweeps_learned_incl_feature_sweep": ml_,
@@ -596,6 +646,8 @@ def main():
         return learned(args)
     if args.workload == "permute":
         return permutes(args)
+    if args.workload == "damping":
+        return damping(args)
     import torch
     from paper_2606_30985_amd import hpt
 
