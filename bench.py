@@ -442,9 +442,11 @@ def learned(args):
             rl.append(ml)
         report.append({"h": h, "sweeps_uniform": su, "sweeps_learned": sl,
                        "mean_sweeps_uniform": sum(su) / len(su), "mean_sweeps_learned": sum(sl) / len(sl),
-                       "max_abs_dC": max(dc),
+                       "max_abs_dC": max(dc), "C_uniform": [r["C"] for r in ru], "C_learned": [r["C"] for r in rl],
                        "traps_uniform": traps.detect_traps(ru, tol=common["meas_tol"])["type1"],
-                       "traps_learned": traps.detect_traps(rl, tol=common["meas_tol"])["type1"]})
+                       "traps_learned": traps.detect_traps(rl, tol=common["meas_tol"])["type1"],
+                       "nonconverged_uniform": traps.detect_traps(ru, tol=common["meas_tol"])["type2"],
+                       "nonconverged_learned": traps.detect_traps(rl, tol=common["meas_tol"])["type2"]})
         print(f"# held-out h={h}: sweeps uniform {sum(su) / len(su):.1f} learned {sum(sl) / len(sl):.1f} "
               f"max|dC| {max(dc):.1e}", file=sys.stderr, flush=True)
         uni.close()
