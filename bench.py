@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--meas-tol", type=float, default=1e-10)
     ap.add_argument("--meas-max-sweeps", type=int, default=400)
     ap.add_argument("--bp-init", default="warm", choices=["warm", "uniform"])
+    ap.add_argument("--autotune-report", default="", help="write the launch autotuner's report to this file")
+    ap.add_argument("--meas-graph", type=int, default=1, choices=[0, 1],
+                    help="1: each measurement sweep replays one HIP graph; 0: direct launches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trace", default="", help="append per-step records (JSON lines) to this file")
     ap.add_argument("--profile-all", action="store_true",
@@ -209,7 +212,7 @@ def batched(args):
     sims = [hpt.Simulator(Lx=r["Lx"], Ly=r["Ly"], J=r["J"], h=r["h"], dt=r["dt"], chi_max=args.batch_chi,
                           precision="fp32", bp_tol=args.bp_tol, bp_max_sweeps=args.bp_max_sweeps, bp_alpha=0.5,
                           bp_init=args.bp_init, meas_tol=args.meas_tol, meas_max_sweeps=args.meas_max_sweeps,
-                          stream=torch.cuda.Stream())
+                          meas_graph=args.meas_graph, stream=torch.cuda.Stream())
             for r in runs]
     nsteps = [r["nsteps"] for r in runs]
     total = sum(nsteps)
@@ -246,7 +249,7 @@ def batched(args):
            "config": {"workload": f"{len(runs)} independent runs, grids 3x3..6x6, h ~ U[0.5,3], dt in "
                                   f"{{0.025,0.05,0.1,0.2}}, t = 2, chi_max={args.batch_chi}, FP32 form",
                       "layers": total, "sequential_layers_per_s": total / t_seq, "speedup_vs_sequential": t_seq / t_bat,
-                      "max_abs_dC_batched_vs_sequential": dmax}}
+                      "max_abs_dC_batched_vs_sequential": dmax, "meas_graph": args.meas_graph}}
     print(json.dumps(out), flush=True)
 
 
@@ -255,10 +258,12 @@ def permutes(args):
     site degree (4 interior, 3 edge, 2 corner) and every cut leg that is not
     already last, the forward move [.., cut, .., P] -> [.., .., cut, P] and its
     inverse, at chi in {20, 40, 60, 100} and one uneven boundary shape, float32
-    and float64 (seeded random data).  Each case: one untimed call, then the
-    mean of 5 calls between HIP events on the launch stream; GB/s = bytes read
-    + bytes written per call / time.  Every result is checked bit for bit
-    against torch's permute."""
+    and float64 (seeded random data).  Each case: one untimed call, six more
+    (synchronised) that let the launch autotuner time its variants and
+    decide, then the mean of 5 calls between HIP events on the launch stream;
+    GB/s = bytes read + bytes written per call / time.  The results of the
+    first and of the timed calls are checked bit for bit against torch's
+    permute."""
     import numpy as np
     import torch
     from paper_2606_30985_amd import hpt
@@ -286,6 +291,9 @@ def permutes(args):
                     ref = x.permute(*perm).permute(*range(deg, -1, -1)).contiguous().view(-1)
                     if not torch.equal(dst, ref):
                         raise SystemExit(f"permute mismatch {name} cut {cut} {direction} {dt}")
+                    for _ in range(6):   # lets the launch autotuner time its variants and decide
+                        hpt.permute(x, dst, perm)
+                        torch.cuda.synchronize()
                     st = torch.cuda.current_stream()
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     e0.record(st)
@@ -293,6 +301,8 @@ def permutes(args):
                         hpt.permute(x, dst, perm)
                     e1.record(st)
                     torch.cuda.synchronize()
+                    if not torch.equal(dst, ref):
+                        raise SystemExit(f"permute mismatch {name} cut {cut} {direction} {dt} (tuned)")
                     ms = e0.elapsed_time(e1) / 5
                     nbytes = 2 * n * src.element_size()
                     rows.append({"shape": name, "dims": d_in, "cut": cut, "dir": direction,
@@ -306,7 +316,7 @@ def permutes(args):
     gb = sorted(r["GBps"] for r in big)
     out = {"metric": "device permutation bandwidth of the gate update (cut leg next to the Pauli leg and back)",
            "value": gb[len(gb) // 2], "unit": "GB/s (median over moves of >= 256 MB)", "n_gpus": 1,
-           "steps": 5, "warmup": 1, "ms_per_step": sum(r["ms"] for r in rows) / len(rows),
+           "steps": 5, "warmup": 7, "ms_per_step": sum(r["ms"] for r in rows) / len(rows),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32/f64 (bit copies)",
            "data": "synthetic (seeded random tensors)",
            "config": {"workload": "every degree, cut leg and direction at chi 20/40/60/100 and one uneven shape",
@@ -491,10 +501,24 @@ def centre_bonds(L):
     return [b for b, (a, d) in enumerate(ends) if (c, c) in (a, d)]
 
 
+def autotune_summary(hpt, path):
+    """Shape classes the launch autotuner decided, and how many of them chose a
+    variant other than the default; the full report goes to path if given."""
+    rep = hpt.autotune_report()
+    if path:
+        with open(path, "w") as f:
+            for site, key, times, choice in rep:
+                f.write(f"{site} {' '.join(map(str, key))}: "
+                        f"{' '.join('-' if t is None else f'{t:.4f}' for t in times)} -> {choice}\n")
+    decided = [r for r in rep if r[3] >= 0]
+    return {"classes": len(rep), "decided": len(decided), "non_default": sum(1 for r in decided if r[3] != 0)}
+
+
 def make_sim(hpt, args, precision, **extra):
     return hpt.Simulator(Lx=args.L, Ly=args.L, chi_max=args.chi, dt=args.dt, J=1.0, h=1.0, precision=precision,
                          bp_tol=args.bp_tol, bp_max_sweeps=args.bp_max_sweeps, bp_alpha=0.5,
-                         meas_tol=args.meas_tol, meas_max_sweeps=args.meas_max_sweeps, bp_init=args.bp_init, **extra)
+                         meas_tol=args.meas_tol, meas_max_sweeps=args.meas_max_sweeps, bp_init=args.bp_init,
+                         meas_graph=args.meas_graph, **extra)
 
 
 def run_layer(sim, torch, tag, trace=None):
@@ -811,6 +835,8 @@ def main():
                                f"then layers {ramp + 1}..{last} of the {last}-layer run repeated from a device "
                                f"snapshot of layer {ramp} ({args.warmup} untimed, {args.steps} timed)",
                    "timed_layers": [r["step"] for r in timed_recs],
+                   "meas_graph": args.meas_graph,
+                   "autotune": autotune_summary(hpt, args.autotune_report),
                    "chi_over_bonds_at_snapshot": cst,
                    "centre_bonds_chi": [chis[b] for b in cb],
                    "bond_updates_per_s": n_bonds * phase["layers"] / gate_s if gate_s > 0 else None,

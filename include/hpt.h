@@ -136,7 +136,10 @@ typedef struct {
                               HPT_BP_LEARNED: warm start proposed by the network given with
                               hpt_set_meas_model (one extra sweep, counted in meas_sweeps,
                               computes its features) */
-  int32_t reserved[1];
+  int32_t meas_graph;      /* 1 (default): every measurement sweep replays one HIP graph of its
+                              kernels; 0: the kernels are launched one by one.  Both queue the
+                              sweeps in batches with the stop test on the device and give the
+                              same results bit for bit */
 } hpt_config;
 
 /* model axes */
@@ -185,18 +188,25 @@ int hpt_reset(hpt_sim* sim);
  * after the last layer's bond dimensions are known on the host. */
 int hpt_step(hpt_sim* sim, int32_t nsteps);
 
-/* One field half-step exp(+i h dt/2 Z) on every site (row a1). */
+/* One field half-step exp(+i h dt/2 Z) on every site (Sec. "Trotter Decomposition", Eq. trotter). */
 int hpt_apply_field(hpt_sim* sim);
 
-/* The two-site gate update of Algorithm "Gate update" on one bond (rows a2-a7). */
+/* The two-site gate update of Algorithm "Gate update" on one bond. */
 int hpt_apply_bond(hpt_sim* sim, int32_t bond);
 
-/* Gauge BP on the norm network until delta < bp_tol or bp_max_sweeps (row a8).
+/* Gauge BP on the norm network until delta < bp_tol or bp_max_sweeps (Sec. "BP Message Update").
  * init: HPT_BP_UNIFORM or HPT_BP_WARM.  sweeps/delta may be NULL. */
 int hpt_gauge_bp(hpt_sim* sim, int32_t init, int32_t* sweeps, double* delta);
 
-/* Measurement BP on the pinned network and log-space Bethe sum (row a9),
- * plus the diagnostics of the last layer.  Synchronises the stream. */
+/* Measurement BP on the pinned network and log-space Bethe sum (Sec. "Correlation Function via
+ * Belief Propagation", Eq. bethe),
+ * plus the diagnostics of the last layer.  Synchronises the stream.  The
+ * sweeps are queued in batches (1, 2, 4, then 8 between host checks), each a
+ * replay of one HIP graph holding a sweep's kernels (captured once per call
+ * on a side stream the handle creates at default priority, launched on the
+ * handle's stream); the residual test runs on the device and sweeps queued
+ * after the converged one do nothing, so C and meas_sweeps are those of a
+ * test after every sweep. */
 int hpt_measure(hpt_sim* sim, hpt_measurement* out);
 
 /* Live bond dimension of one bond. */
@@ -260,9 +270,9 @@ int hpt_checkpoint_load(hpt_sim* sim, const void* buf, uint64_t bytes, int32_t w
 /* Per-phase timing of one handle with HIP events on its stream (the benchmark's
  * split of a layer): enable = 1 creates the events and clears the totals,
  * 0 removes them.  While enabled, every layer adds the milliseconds of its
- * gate phase (both field half-steps and the four colours, rows a1-a7) and of
- * its gauge BP (row a8), and every hpt_measure those of the measurement BP
- * and Bethe sum (row a9); each phase boundary waits for its event.
+ * gate phase (both field half-steps and the four colours) and of
+ * its gauge BP, and every hpt_measure those of the measurement BP
+ * and Bethe sum; each phase boundary waits for its event.
  * hpt_phase_read fills out7 = {gate ms, gauge-BP ms, measurement ms, layers,
  * gauge sweeps, measurements, measurement sweeps}. */
 int hpt_phase_timing(hpt_sim* sim, int32_t enable);
@@ -386,6 +396,42 @@ int hpt_gram64_noalloc(const float* X, int64_t m, int32_t n, int64_t ldx, double
  * result registers), device.  Shows how the instruction rounds the float32
  * sum of its products (tests/test_gpu_bsplit_rounding.py). */
 int hpt_bf16_mfma_sum(const float* a, float c, float* out, void* hip_stream);
+
+/* Float32 mode product of the gate update's absorb step (Sec. "Gate Update"
+ * item 1: a square root of an environment message applied to one leg of a
+ * site tensor) and of the gauge-BP environment products, the kernels the
+ * float32 form runs:
+ *   dst[a, j, b] = sum_{k < n} S[j, k] src[a, k, b],  a < inner, b < outer,
+ * all column-major float32 on the device (S n x n; src, dst inner x n x outer,
+ * not overlapping).  Float32 MFMA products with float32 accumulation in
+ * increasing k (groups of 4), so equal inputs give equal outputs bit for bit.
+ * Shapes the MFMA kernels serve: 1 <= n <= 128, and inner == 1 with
+ * outer >= 16 (the leading leg) or 16 <= inner with inner n < 2^30; other
+ * shapes (and null pointers) return HPT_EINVAL before any launch.
+ * Stream-ordered on hip_stream, asynchronous; HPT_EHIP when a launch fails. */
+int hpt_mode_product_f32(const float* src, float* dst, const float* S, int32_t n, int64_t inner, int64_t outer,
+                         void* hip_stream);
+
+/* Launch-shape autotuner.  Some launches of the layer have variants that
+ * compute every output with the same operations in the same order (so the
+ * choice changes the time, never a result): the mode products of the absorb
+ * step and of the gauge-BP environment products (32-row strips on the
+ * resident grid or on two thirds of it, or 16-row strips; the leading leg:
+ * the resident grid or two thirds of it) and the cut-leg moves from or to the
+ * first position (Sec. "GPU Tensor Permutation": LDS panel transposes or
+ * 64 x 64 tiles).  Per shape class the first calls run the variants in turn,
+ * timed by HIP events read later without blocking; once each has been timed
+ * twice the fastest is kept for the rest of the process.  Process-wide (all
+ * handles and threads).
+ * hpt_autotune: mode 1 = on (the default), 0 = off (the default variant
+ *   everywhere), 2 = forget every measurement and decision.  HPT_EINVAL for
+ *   another mode.
+ * hpt_autotune_report: one text line per shape class, "site k0 k1 k2: t0 t1
+ *   ... -> choice" (the best milliseconds of each variant, "-" when not yet
+ *   timed; choice -1 while tuning), NUL-terminated and truncated to cap
+ *   bytes; *needed (may be NULL) receives the full length + 1. */
+int hpt_autotune(int32_t mode);
+int hpt_autotune_report(char* buf, uint64_t cap, uint64_t* needed);
 
 /* Permute a column-major tensor on the device (Sec. "GPU Tensor Permutation").
  * in/out: device pointers, not overlapping; ndim <= 8; dims of the input;

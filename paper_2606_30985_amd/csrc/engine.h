@@ -91,6 +91,7 @@ struct hpt_sim {
   std::vector<int> chi;
   std::vector<std::vector<double>> lam;
   hipStream_t stream;
+  hipStream_t cap_stream = nullptr;   // side stream for capturing the measurement sweep graph
   char* arena;
   uint64_t arena_bytes;
   bool own_arena;
@@ -112,7 +113,7 @@ struct hpt_sim {
   double cfg_qr_tol;
   // small device arrays
   double* bethe_x;      // N + nb values
-  double* res;          // 8 doubles
+  double* res;          // 16 doubles: [0..4] log product, [8..9] measurement sweep control, [12..] Jacobi state
   double* delta;        // 2 nb
   hpt::BondCore* cores_dev;
   // job staging
@@ -146,6 +147,6 @@ struct hpt_sim {
   // per-phase timing (hpt_phase_timing): HIP events on the handle's stream
   bool phase_on;
   hipEvent_t phase_ev[5];
-  double phase_ms[3];           // gate phase (rows a1-a7), gauge BP (a8), measurement (a9)
+  double phase_ms[3];           // gate phase (field half-steps and gate updates), gauge BP, measurement
   int64_t phase_count[4];       // layers, gauge sweeps, measurements, measurement sweeps
 };

@@ -95,6 +95,7 @@ int validate(const hpt_config* c) {
   if (c->trap_alpha > 1.0 || c->trap_sweeps < 1) return HPT_EINVAL;
   if (c->bp_init != HPT_BP_UNIFORM && c->bp_init != HPT_BP_WARM) return HPT_EINVAL;
   if (c->meas_init != HPT_BP_UNIFORM && c->meas_init != HPT_BP_LEARNED) return HPT_EINVAL;
+  if (c->meas_graph != 0 && c->meas_graph != 1) return HPT_EINVAL;
   if (c->model_axes != HPT_AXES_PAPER && c->model_axes != HPT_AXES_ZZX) return HPT_EINVAL;
   if (c->svd_max_sweeps < 0) return HPT_EINVAL;
   // the storage of one interior site must stay addressable with 64-bit offsets
@@ -413,7 +414,7 @@ double* mmsg_hat_slot(hpt_sim* s, int b, int dir) { return s->mmsg_hat + (uint64
 int dir_from(hpt_sim* s, int b, int src) { return s->bonds[b].v1 == src ? 0 : 1; }
 
 // ---------------------------------------------------------------------------
-// row a1: field half-step
+// field half-step (Sec. "Trotter Decomposition", Eq. trotter)
 template <typename T>
 int apply_field_t(hpt_sim* s) {
   for (int v = 0; v < s->N; ++v) {
@@ -427,7 +428,7 @@ int apply_field_t(hpt_sim* s) {
 }
 
 // ---------------------------------------------------------------------------
-// rows a2..a7: gate update of every bond of one colour
+// gate update (Algorithm "Gate update") of every bond of one colour
 struct SitePlan {
   int v, cut, deg;
   int64_t dims[5];
@@ -1223,7 +1224,7 @@ int gate_colour(hpt_sim* s, const std::vector<int>& cbonds) {
 }
 
 // ---------------------------------------------------------------------------
-// row a8: gauge BP on the norm network
+// gauge BP on the norm network (Sec. "BP Message Update", Eq. bp)
 
 template <typename T>
 const T* gmsg_T(hpt_sim* s, int b, int dir);
@@ -1334,39 +1335,40 @@ int gauge_bp_t(hpt_sim* s, int init, int* sweeps_out, double* delta_out) {
 }
 
 // ---------------------------------------------------------------------------
-// row a9: measurement BP and the log-space Bethe sum
+// measurement BP and the log-space Bethe sum (Sec. "Correlation Function via Belief
+// Propagation", Eq. bethe)
 
-template <typename T>
-int meas_outgoing(hpt_sim* s, bool only_first_leg) {
-  // Per site, one read of the pinned slice T_v gives the last leg's outgoing
-  // message and P = T_v contracted with the last leg's incoming message;
-  // the other legs' outgoing messages come from P (float64, 1/chi of the
-  // slice) through the generic contraction jobs.  Sites are batched within
-  // the scratch and partial budgets.
+// The launches of one measurement sweep: groups of sites whose scratch fits
+// the measurement scratch and partial budgets, each one last-leg launch and
+// one contraction launch.  The job arrays do not change between sweeps of one
+// BP, so they are planned once, staged once per batch of sweeps and launched
+// again for every sweep of the batch.
+struct MeasGroup {
   std::vector<LastLegJob> ll;
-  std::vector<MeasJob> batch;
+  int64_t ll_blocks = 0;
+  int max_nl = 1;
+  std::vector<MeasJob> mj;
+  int64_t totals[4] = {0, 0, 0, 0};
+  LastLegJob* ll_dev = nullptr;
+  MeasJob* mj_dev = nullptr;
+};
+
+// Per site, one read of the pinned slice T_v gives the last leg's outgoing
+// message and P = T_v contracted with the last leg's incoming message; the
+// other legs' outgoing messages come from P (float64, 1/chi of the slice)
+// through the generic contraction jobs.
+template <typename T>
+int meas_sweep_plan(hpt_sim* s, bool only_first_leg, std::vector<MeasGroup>& groups) {
+  groups.clear();
+  groups.emplace_back();
   int64_t used = 0, pused = 0;
-  auto flush = [&]() -> int {
-    if (!ll.empty()) {
-      int max_nl = 1;
-      const int64_t blocks = last_leg_plan(ll.data(), (int)ll.size(), s->fp32 ? 0 : 1, &max_nl);
-      if (blocks < 0) return HPT_EINVAL;
-      LastLegJob* ld;
-      RC(stage(s, ll.data(), (int)ll.size(), &ld));
-      KR(launch_last_leg(ld, (int)ll.size(), blocks, max_nl, s->fp32 ? 0 : 1, s->stream));
+  auto close = [&]() -> int {
+    MeasGroup& g = groups.back();
+    if (!g.ll.empty()) {
+      g.ll_blocks = last_leg_plan(g.ll.data(), (int)g.ll.size(), s->fp32 ? 0 : 1, &g.max_nl);
+      if (g.ll_blocks < 0) return HPT_EINVAL;
     }
-    if (!batch.empty()) {
-      int64_t totals[4];
-      const int64_t pneed = meas_plan(batch.data(), (int)batch.size(), totals);
-      if (pneed > s->cv.part_cap) return HPT_ENOMEM;
-      MeasJob* jd;
-      RC(stage(s, batch.data(), (int)batch.size(), &jd));
-      KR(meas_launch(jd, (int)batch.size(), totals, 1, s->part, s->stream));
-    }
-    ll.clear();
-    batch.clear();
-    used = 0;
-    pused = 0;
+    if (!g.mj.empty() && meas_plan(g.mj.data(), (int)g.mj.size(), g.totals) > s->cv.part_cap) return HPT_ENOMEM;
     return 0;
   };
   auto in_msg = [&](const SiteInfo& si, int l) { return mmsg_slot(s, si.bond[l], dir_from(s, si.bond[l], si.nbr[l])); };
@@ -1419,24 +1421,114 @@ int meas_outgoing(hpt_sim* s, bool only_first_leg) {
       js.push_back(j);
     }
     if (need > s->cv.meas_scr_cap || pjob > s->cv.part_cap) return HPT_ENOMEM;
-    if (used + need > s->cv.meas_scr_cap || pused + pjob > s->cv.part_cap || ll.size() >= 1024 ||
-        batch.size() + js.size() > 4096)
-      RC(flush());
+    MeasGroup* g = &groups.back();
+    if (used + need > s->cv.meas_scr_cap || pused + pjob > s->cv.part_cap || g->ll.size() >= 1024 ||
+        g->mj.size() + js.size() > 4096) {
+      RC(close());
+      groups.emplace_back();
+      g = &groups.back();
+      used = 0;
+      pused = 0;
+    }
     lj.P = s->meas_scr + used;
     lj.part = lj.P + rows;
     used += rows + llb * dims[L];
-    ll.push_back(lj);
+    g->ll.push_back(lj);
     for (MeasJob& j : js) {
       j.T = lj.P;
       j.x = s->meas_scr + used;
       j.y = j.x + j.I;
       j.S = j.y + j.O;
       used += j.I + j.O + (j.O > 1 ? j.I * j.nk : 0);
-      batch.push_back(j);
+      g->mj.push_back(j);
     }
     pused += pjob;
   }
-  return flush();
+  return close();
+}
+
+// bytes the staged arrays of a sweep take in the job region
+uint64_t meas_stage_bytes(const std::vector<MeasGroup>& groups) {
+  uint64_t b = 0;
+  for (const MeasGroup& g : groups)
+    b += align_up(sizeof(LastLegJob) * std::max<size_t>(g.ll.size(), 1)) +
+         align_up(sizeof(MeasJob) * std::max<size_t>(g.mj.size(), 1));
+  return b;
+}
+
+// stage every group's arrays (extra: bytes of further arrays the caller stages
+// with them; a sync first if they would not all fit, so no stage call of the
+// batch recycles the region)
+int meas_sweep_stage(hpt_sim* s, std::vector<MeasGroup>& groups, uint64_t extra) {
+  const uint64_t need = meas_stage_bytes(groups) + extra;
+  if (need > s->cv.jobs_bytes) return HPT_ENOMEM;
+  if (s->jobs_used + need > s->cv.jobs_bytes) RC(sync_stream(s));
+  for (MeasGroup& g : groups) {
+    if (!g.ll.empty()) RC(stage(s, g.ll.data(), (int)g.ll.size(), &g.ll_dev));
+    if (!g.mj.empty()) RC(stage(s, g.mj.data(), (int)g.mj.size(), &g.mj_dev));
+  }
+  return 0;
+}
+
+// launch one sweep's outgoing-message contractions from the staged arrays
+int meas_sweep_launch(hpt_sim* s, const std::vector<MeasGroup>& groups, const double* stop) {
+  for (const MeasGroup& g : groups) {
+    if (!g.ll.empty())
+      KR(launch_last_leg(g.ll_dev, (int)g.ll.size(), g.ll_blocks, g.max_nl, s->fp32 ? 0 : 1, s->stream, stop));
+    if (!g.mj.empty()) KR(meas_launch(g.mj_dev, (int)g.mj.size(), g.totals, 1, s->part, s->stream, stop));
+  }
+  return 0;
+}
+
+// One sweep's launches captured from a stream into an executable HIP graph
+// (kernels only: no memset or copy nodes), replayed on the same stream;
+// destroyed with the object.
+struct SweepGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  SweepGraph() = default;
+  SweepGraph(const SweepGraph&) = delete;
+  SweepGraph& operator=(const SweepGraph&) = delete;
+  ~SweepGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+  template <typename F>
+  int capture(hipStream_t st, F&& launches) {
+    HPT_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    const int rc = launches();
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc) return rc;
+    HPT_HIP(e);
+    HPT_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    return 0;
+  }
+  int launch(hipStream_t st) {
+    HPT_HIP(hipGraphLaunch(exec, st));
+    return 0;
+  }
+};
+
+// Capture on the handle's own side stream (default priority; the handle's
+// stream may be the null stream, which cannot be captured): the launch
+// helpers target s->stream, so it points at the side stream meanwhile.  The
+// graph is then launched on s->stream.
+template <typename F>
+int capture_sweep(hpt_sim* s, SweepGraph& g, F&& launches) {
+  if (!s->cap_stream) HPT_HIP(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+  hipStream_t keep = s->stream;
+  s->stream = s->cap_stream;
+  const int rc = g.capture(s->cap_stream, launches);
+  s->stream = keep;
+  return rc;
+}
+
+template <typename T>
+int meas_outgoing(hpt_sim* s, bool only_first_leg) {
+  std::vector<MeasGroup> groups;
+  RC(meas_sweep_plan<T>(s, only_first_leg, groups));
+  RC(meas_sweep_stage(s, groups, 0));
+  return meas_sweep_launch(s, groups, nullptr);
 }
 
 // One measurement BP (fresh uniform start, damping alpha) and the Bethe sum.
@@ -1542,22 +1634,44 @@ int meas_bp_t(hpt_sim* s, double alpha, MeasResult& mr, bool learned = false, bo
     for (int d = 0; d < 2; ++d) nj[2 * b + d] = MeasNormJob{mmsg_slot(s, b, d), mmsg_hat_slot(s, b, d), s->chi[b]};
   const double tol = s->cfg.meas_tol > 0.0 ? s->cfg.meas_tol : s->cfg.bp_tol;
   const int maxs = s->cfg.meas_max_sweeps > 0 ? s->cfg.meas_max_sweeps : s->cfg.bp_max_sweeps;
-  int sweeps = 0;
+  // Sweeps are queued in batches of 1, 2, 4, then 8 between host checks: the
+  // residual test runs on the device (ctl: stop flag, sweeps taken), sweeps
+  // queued past the converged one do nothing, so the result and the sweep
+  // count are those of a host check after every sweep.
+  // The job arrays are staged once for the whole BP (nothing else is staged
+  // until it ends, so the syncs between batches leave them in place) and one
+  // sweep's launches are captured in a HIP graph that every sweep replays.
+  std::vector<MeasGroup> groups;
+  RC(meas_sweep_plan<T>(s, false, groups));
+  double* ctl = s->res + 8;
+  KR(launch_fill_value(ctl, 2, 0.0, s->stream));
+  RC(meas_sweep_stage(s, groups, align_up(sizeof(MeasNormJob) * nbd)));
+  MeasNormJob* njd;
+  RC(stage(s, nj.data(), nbd, &njd));
+  auto one_sweep = [&]() -> int {
+    RC(meas_sweep_launch(s, groups, ctl));
+    KR(launch_meas_norm(njd, nbd, alpha, s->delta, s->stream, ctl));
+    KR(launch_log_product(s->bethe_x, 0, 0, s->delta, nbd, s->res, s->stream, tol, ctl));
+    return 0;
+  };
+  SweepGraph sg;
+  const bool graph = s->cfg.meas_graph != 0;
+  if (graph) RC(capture_sweep(s, sg, one_sweep));
+  int sweeps = 0, queued = 0, batch = 1;
   double delta = INFINITY;
-  double res[5];
-  while (sweeps < maxs) {
-    RC(meas_outgoing<T>(s, false));
-    MeasNormJob* njd;
-    RC(stage(s, nj.data(), nbd, &njd));
-    KR(launch_meas_norm(njd, nbd, alpha, s->delta, s->stream));
-    KR(launch_log_product(s->bethe_x, 0, 0, s->delta, nbd, s->res, s->stream));
-    HPT_HIP(hipMemcpyAsync(s->hscratch, s->res, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  double res[10];
+  while (queued < maxs) {
+    const int nq = std::min(batch, maxs - queued);
+    for (int q = 0; q < nq; ++q) RC(graph ? sg.launch(s->stream) : one_sweep());
+    queued += nq;
+    HPT_HIP(hipMemcpyAsync(s->hscratch, s->res, sizeof(res), hipMemcpyDeviceToHost, s->stream));
     RC(sync_stream(s));
     std::memcpy(res, s->hscratch, sizeof(res));
     delta = res[4];
-    ++sweeps;
-    if (!std::isfinite(delta)) return HPT_ENUMERIC;
-    if (delta < tol) break;
+    sweeps = (int)res[9];
+    if (sweeps > 0 && !std::isfinite(delta)) return HPT_ENUMERIC;
+    if (res[8] != 0.0) break;
+    batch = std::min(2 * batch, 8);
   }
   // Bethe: vs_v = <out_{v -> leg0}, m_{leg0 -> v}>, Z_e = <m_{b,0}, m_{b,1}>
   RC(meas_outgoing<T>(s, true));
@@ -1790,6 +1904,7 @@ int hpt_config_default(hpt_config* c) {
   c->qr_rank_tol = -1.0;
   c->trap_retry = 0;
   c->trap_alpha = -1.0;
+  c->meas_graph = 1;
   return HPT_OK;
 }
 
@@ -2376,6 +2491,7 @@ int hpt_destroy(hpt_sim* s) {
     for (hipEvent_t e : s->phase_ev) (void)hipEventDestroy(e);
   if (s->jobs_host) (void)hipHostFree(s->jobs_host);
   if (s->hscratch) (void)hipHostFree(s->hscratch);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->own_arena && s->arena) (void)hipFree(s->arena);
   delete s;
   return HPT_OK;

@@ -14,6 +14,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "tune.h"
 
 namespace hpt {
 
@@ -706,18 +707,23 @@ __global__ __launch_bounds__(256) void mode_product_kernel(const float* __restri
 // MFMAs that share the factor operand, so block h of the result holds rows
 // 2 r16 + h and the float2 stores of 16 lanes cover 128 contiguous bytes of a
 // column (the 16-row form moves 64-byte pieces); half the load and factor
-// read instructions per MFMA.  Every output element sees the same MFMA
-// operands in the same k order as in the 16-row form.
+// read instructions per MFMA.  The factor is staged so that the NB <= 8
+// values a lane needs at one k (rows j = 16 cb + r16) are two 16-byte LDS
+// reads: Sl[k][h][r][c] = S[16 (4 h + c) + r, k] (each read of 16 lanes
+// covers 256 contiguous bytes), only the 4 KS rows k the strip loop uses.
+// Every output element sees the same MFMA operands in the same k order as in
+// the 16-row form.
 template <int NP, int KS>
-__global__ __launch_bounds__(256) void mode_product32_kernel(const float* __restrict__ src, float* __restrict__ dst,
+__global__ __launch_bounds__(256, 3) void mode_product32_kernel(const float* __restrict__ src, float* __restrict__ dst,
                                                              const float* __restrict__ S, int n, int64_t inner,
                                                              int64_t Z, int64_t strips_per_z) {
   constexpr int NB = NP / 16;
-  constexpr int SP = NP + ((NP % 32) == 0 ? 16 : 0);   // row stride = 16 mod 32
-  __shared__ float Sl[NP * SP];                         // Sl[k * SP + j] = S[j, k]
-  for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
-    const int j = idx % NP, k = idx / NP;
-    Sl[k * SP + j] = (j < n && k < n) ? S[j + (int64_t)k * n] : 0.f;
+  static_assert(NB <= 8, "two 16-byte factor reads per k");
+  __shared__ float Sl[KS * 4 * 128];
+  for (int idx = threadIdx.x; idx < KS * 4 * 128; idx += blockDim.x) {
+    const int k = idx >> 7, cb = ((idx >> 6) & 1) * 4 + (idx & 3), r = (idx >> 2) & 15;
+    const int j = cb * 16 + r;
+    Sl[idx] = (cb < NB && j < n && k < n) ? S[j + (int64_t)k * n] : 0.f;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
@@ -726,14 +732,17 @@ __global__ __launch_bounds__(256) void mode_product32_kernel(const float* __rest
   float2 y[KS];
   // rows past the end read the clamped, in-range pair inner - 2, inner - 1
   // (never stored); k >= n read k = n - 1 (the factor's rows k >= n are zero)
-  auto fetch = [&](int64_t st, float2* v) {
+  // opk is an opaque zero made inside the strip loop: without it the 25
+  // loop-invariant row offsets k inner are hoisted out of the loop and held in
+  // registers (spilled at three waves per SIMD)
+  auto fetch = [&](int64_t st, float2* v, int opk) {
     const int64_t z = st / strips_per_z;
     const int64_t r = (st % strips_per_z) * 32 + 2 * r16;
     const uint32_t row = (uint32_t)(r < inner ? r : inner - 2);
     const char* base = (const char*)(src + z * inner * n);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const uint32_t k = (uint32_t)min(ks * 4 + kq, n - 1);
+      const uint32_t k = (uint32_t)min(ks * 4 + kq + opk, n - 1);
       v[ks] = *(const float2*)(base + (row + k * (uint32_t)inner) * 4u);
     }
   };
@@ -741,7 +750,9 @@ __global__ __launch_bounds__(256) void mode_product32_kernel(const float* __rest
   // 350 MFMAs per wave, and the other waves of the SIMD cover its load latency
   int64_t st = blockIdx.x * (int64_t)(blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (; st < total; st += nwaves) {
-    fetch(st, y);
+    int opk = 0;
+    asm volatile("" : "+v"(opk));
+    fetch(st, y, opk);
     f4 acc0[NB], acc1[NB];
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
@@ -752,10 +763,12 @@ __global__ __launch_bounds__(256) void mode_product32_kernel(const float* __rest
     asm volatile("" : "+v"(opq));
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const float* Sk = Sl + opq + (ks * 4 + kq) * SP + r16;
+      const float* Sk = Sl + opq + (ks * 4 + kq) * 128 + 4 * r16;
+      const f4 lo = *(const f4*)Sk;
+      const f4 hi = NB > 4 ? *(const f4*)(Sk + 64) : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) {
-        const float a = Sk[cb * 16];
+        const float a = cb < 4 ? lo[cb & 3] : hi[cb & 3];
         acc0[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, y[ks].x, acc0[cb], 0, 0, 0);
         acc1[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, y[ks].y, acc1[cb], 0, 0, 0);
       }
@@ -763,13 +776,14 @@ __global__ __launch_bounds__(256) void mode_product32_kernel(const float* __rest
     const int64_t z = st / strips_per_z;
     const int64_t row = (st % strips_per_z) * 32 + 2 * r16;
     if (row < inner) {
-      float* Cz = dst + z * inner * n + row;
+      char* Cz = (char*)(dst + z * inner * n);
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int col = cb * 16 + 4 * kq + e;
-          if (col < n) *(float2*)(Cz + (int64_t)col * inner) = make_float2(acc0[cb][e], acc1[cb][e]);
+          const uint32_t col = (uint32_t)(cb * 16 + 4 * kq + e + opk);
+          if (col < (uint32_t)n)
+            *(float2*)(Cz + ((uint32_t)row + col * (uint32_t)inner) * 4u) = make_float2(acc0[cb][e], acc1[cb][e]);
         }
     }
   }
@@ -780,16 +794,21 @@ __global__ __launch_bounds__(256) void mode_product32_kernel(const float* __rest
 // n % 4 == 0); the MFMA's reduction index is permuted accordingly (lane
 // group kq supplies k = 16 kb + 4 kq + t at step t, and reads the same k of
 // the factor), and the result blocks are dst^T, so stores run along j.
-// 16-column strips, next strip fetched during the current one's MFMAs.
+// 16-column strips, next strip fetched during the current one's MFMAs.  The
+// factor sits in dynamic LDS as rows of 128 floats, Sl[k][h][r][c] =
+// S[16 (4 h + c) + r, k] for k < n and one zero row k = n that every k >= n
+// reads: the NB <= 8 values a lane needs at one k are two 16-byte reads.
 template <int NP, bool VEC>
 __global__ __launch_bounds__(256) void mode_product_lead_kernel(const float* __restrict__ src, float* __restrict__ dst,
                                                                 const float* __restrict__ S, int n, int64_t outer) {
   constexpr int NB = NP / 16, KB = NP / 16;
-  constexpr int SP = NP + ((NP % 8) == 0 ? 4 : 0);    // row stride = 4 mod 8
-  __shared__ float Sl[NP * SP];                        // Sl[k * SP + j] = S[j, k]
-  for (int idx = threadIdx.x; idx < NP * NP; idx += blockDim.x) {
-    const int j = idx % NP, k = idx / NP;
-    Sl[k * SP + j] = (j < n && k < n) ? S[j + (int64_t)k * n] : 0.f;
+  static_assert(NB <= 8, "two 16-byte factor reads per k");
+  extern __shared__ float Sl[];
+  const int rows = n < NP ? n + 1 : NP;
+  for (int idx = threadIdx.x; idx < rows * 128; idx += blockDim.x) {
+    const int k = idx >> 7, cb = ((idx >> 6) & 1) * 4 + (idx & 3), r = (idx >> 2) & 15;
+    const int j = cb * 16 + r;
+    Sl[idx] = (cb < NB && j < n && k < n) ? S[j + (int64_t)k * n] : 0.f;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
@@ -829,9 +848,12 @@ __global__ __launch_bounds__(256) void mode_product_lead_kernel(const float* __r
     for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const float* Sk = Sl + opq + (kb * 16 + 4 * kq + t) * SP + r16;
+        const float* Sk = Sl + min(kb * 16 + 4 * kq + t + opq, n) * 128 + 4 * r16;
+        const f4 lo = *(const f4*)Sk;
+        const f4 hi = NB > 4 ? *(const f4*)(Sk + 64) : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[kb][t], Sk[cb * 16], acc[cb], 0, 0, 0);
+        for (int cb = 0; cb < NB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[kb][t], cb < 4 ? lo[cb & 3] : hi[cb & 3], acc[cb], 0, 0, 0);
       }
     // block cb, register e: dst[16 cb + r16, b0 + 4 kq + e]
     const int64_t b0 = st * 16;
@@ -1313,7 +1335,7 @@ template int gemm<double>(const GemmDesc<double>&, double*, int64_t, hipStream_t
 template int gemm<float>(const GemmDesc<float>&, double*, int64_t, hipStream_t);
 
 namespace {
-int resident_grid(const void* kernel, int threads, int64_t work_waves) {
+int resident_grid(const void* kernel, int threads, int64_t work_waves, size_t lds = 0) {
   static int cus = 0;
   if (!cus) {
     int dev = 0;
@@ -1321,26 +1343,40 @@ int resident_grid(const void* kernel, int threads, int64_t work_waves) {
       cus = 256;
   }
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess || per_cu < 1) per_cu = 1;
   const int64_t need = ceil_div(work_waves, threads / 64);
   return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * per_cu));
 }
 
 template <int NP, int KS = NP / 4>
 int launch_mode(const float* src, float* dst, const float* S, int n, int64_t inner, int64_t outer, hipStream_t s) {
+  // Variants the autotuner chooses from (the same MFMAs in the same order for
+  // every output): leading leg, the resident grid or two thirds of it; even
+  // inner >= 32, 32-row strips on the resident grid or two thirds of it, or
+  // 16-row strips.
+  TuneCall tc;
   if (inner == 1) {
     const int64_t strips = ceil_div(outer, 16);
+    const size_t lds = (size_t)(n < NP ? n + 1 : NP) * 128 * sizeof(float);
+    const int cand = tune_pick(TUNE_MODE_LEAD, n, inner, outer, 2, &tc);
+    tune_begin(&tc, s);
     if (n % 4 == 0) {
-      const int g = resident_grid((const void*)mode_product_lead_kernel<NP, true>, 256, strips);
-      hipLaunchKernelGGL((mode_product_lead_kernel<NP, true>), dim3(g), dim3(256), 0, s, src, dst, S, n, outer);
+      int g = resident_grid((const void*)mode_product_lead_kernel<NP, true>, 256, strips, lds);
+      if (cand == 1) g = std::max(1, 2 * g / 3);
+      hipLaunchKernelGGL((mode_product_lead_kernel<NP, true>), dim3(g), dim3(256), lds, s, src, dst, S, n, outer);
     } else {
-      const int g = resident_grid((const void*)mode_product_lead_kernel<NP, false>, 256, strips);
-      hipLaunchKernelGGL((mode_product_lead_kernel<NP, false>), dim3(g), dim3(256), 0, s, src, dst, S, n, outer);
+      int g = resident_grid((const void*)mode_product_lead_kernel<NP, false>, 256, strips, lds);
+      if (cand == 1) g = std::max(1, 2 * g / 3);
+      hipLaunchKernelGGL((mode_product_lead_kernel<NP, false>), dim3(g), dim3(256), lds, s, src, dst, S, n, outer);
     }
   } else {
-    if (inner % 2 == 0 && inner >= 32) {
+    const bool even32 = inner % 2 == 0 && inner >= 32 && inner * n < ((int64_t)1 << 30);   // 32-bit byte offsets
+    const int cand = even32 ? tune_pick(TUNE_MODE_STRIPS, n, inner, outer, 3, &tc) : 2;
+    tune_begin(&tc, s);
+    if (cand < 2) {
       const int64_t spz = ceil_div(inner, 32);
-      const int g = resident_grid((const void*)mode_product32_kernel<NP, KS>, 256, spz * outer);
+      int g = resident_grid((const void*)mode_product32_kernel<NP, KS>, 256, spz * outer);
+      if (cand == 1) g = std::max(1, 2 * g / 3);
       hipLaunchKernelGGL((mode_product32_kernel<NP, KS>), dim3(g), dim3(256), 0, s, src, dst, S, n, inner, outer,
                          spz);
     } else {
@@ -1349,6 +1385,7 @@ int launch_mode(const float* src, float* dst, const float* S, int n, int64_t inn
       hipLaunchKernelGGL((mode_product_kernel<NP, KS>), dim3(g), dim3(256), 0, s, src, dst, S, n, inner, outer, spz);
     }
   }
+  tune_end(&tc, s);
   HPT_LAUNCH_CHECK("mode_product_kernel");
   return 0;
 }

@@ -1,4 +1,4 @@
-// Elementwise and reduction kernels: field half-step (row a1), BP message
+// Elementwise and reduction kernels: field half-step (Sec. "Trotter Decomposition"), BP message
 // normalisation and damping (Eq. bp, Eq. bp_tol, Eq. damping), measurement
 // contractions of the pinned network (Sec. "Correlation Function via Belief
 // Propagation", Eq. bethe_raw), the log-space sum with sign tracking
@@ -132,9 +132,16 @@ __global__ __launch_bounds__(256) void dots_kernel(const DotJob* jobs) {
   if (threadIdx.x == 0) *job.out = r;
 }
 
+// Sweep gate of the measurement BP: the kernels of a sweep return at once
+// when the flag a previous sweep's log_product_kernel raised is set (stop
+// null: always run).  The flag is written only between kernels, so every
+// workgroup of one launch sees the same value.
+__device__ __forceinline__ bool stopped(const double* stop) { return stop && *(const volatile double*)stop != 0.0; }
+
 __global__ __launch_bounds__(256) void log_product_kernel(const double* x, int n_num, int n_den,
                                                           const double* delta, int n_delta,
-                                                          double* res) {
+                                                          double* res, double tol, double* ctl) {
+  if (stopped(ctl)) return;
   __shared__ double sh[16];
   double part = 0.0, neg = 0.0, zn = 0.0, zd = 0.0, dmax = 0.0;
   for (int i = threadIdx.x; i < n_num + n_den; i += blockDim.x) {
@@ -160,6 +167,10 @@ __global__ __launch_bounds__(256) void log_product_kernel(const double* x, int n
     res[2] = a;
     res[3] = b;
     res[4] = d;
+    if (ctl) {   // one more sweep taken; stop at convergence or a non-finite residual
+      ctl[1] += 1.0;
+      if (d < tol || !isfinite(d)) ctl[0] = 1.0;
+    }
   }
 }
 
@@ -179,7 +190,8 @@ __device__ inline int find_job(const MeasJob* jobs, int njobs, int64_t b, int wh
   return lo;
 }
 
-__global__ void meas_kron_kernel(const MeasJob* jobs, int njobs) {
+__global__ void meas_kron_kernel(const MeasJob* jobs, int njobs, const double* stop) {
+  if (stopped(stop)) return;
   const int j = find_job(jobs, njobs, blockIdx.x, 0);
   const MeasJob& job = jobs[j];
   const int64_t idx = (blockIdx.x - job.bk0) * (int64_t)blockDim.x + threadIdx.x;
@@ -199,7 +211,8 @@ __global__ void meas_kron_kernel(const MeasJob* jobs, int njobs) {
 
 // part[pn_off + oc * rows + r] = sum_{o in chunk oc} T[r + rows * o] y[o]
 template <typename T>
-__global__ void meas_gemv_n_kernel(const MeasJob* jobs, int njobs, double* part) {
+__global__ void meas_gemv_n_kernel(const MeasJob* jobs, int njobs, double* part, const double* stop) {
+  if (stopped(stop)) return;
   const int j = find_job(jobs, njobs, blockIdx.x, 1);
   const MeasJob& job = jobs[j];
   const int64_t rows = job.I * job.nk;
@@ -216,7 +229,8 @@ __global__ void meas_gemv_n_kernel(const MeasJob* jobs, int njobs, double* part)
   part[job.pn_off + oc * rows + r] = acc;
 }
 
-__global__ void meas_gemv_n_reduce(const MeasJob* jobs, int njobs, const double* part) {
+__global__ void meas_gemv_n_reduce(const MeasJob* jobs, int njobs, const double* part, const double* stop) {
+  if (stopped(stop)) return;
   const int j = find_job(jobs, njobs, blockIdx.x, 3);
   const MeasJob& job = jobs[j];
   const int64_t rows = job.I * job.nk;
@@ -230,7 +244,9 @@ __global__ void meas_gemv_n_reduce(const MeasJob* jobs, int njobs, const double*
 
 // part[pt_off + a * nich + ic] = sum_{i in chunk ic} S[i + I a] x[i]; one wave per (a, ic)
 template <typename T>
-__global__ __launch_bounds__(256) void meas_gemv_t_kernel(const MeasJob* jobs, int njobs, double* part) {
+__global__ __launch_bounds__(256) void meas_gemv_t_kernel(const MeasJob* jobs, int njobs, double* part,
+                                                          const double* stop) {
+  if (stopped(stop)) return;
   const int j = find_job(jobs, njobs, blockIdx.x, 2);
   const MeasJob& job = jobs[j];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -252,7 +268,8 @@ __global__ __launch_bounds__(256) void meas_gemv_t_kernel(const MeasJob* jobs, i
   if (lane == 0) part[job.pt_off + a * nich + ic] = acc;
 }
 
-__global__ void meas_gemv_t_reduce(const MeasJob* jobs, const double* part) {
+__global__ void meas_gemv_t_reduce(const MeasJob* jobs, const double* part, const double* stop) {
+  if (stopped(stop)) return;
   const MeasJob& job = jobs[blockIdx.x];
   const int64_t nich = ceil_div(job.I, 64 * MEAS_CHUNK);
   for (int64_t a = threadIdx.x; a < job.nk; a += blockDim.x) {
@@ -374,7 +391,8 @@ __device__ __forceinline__ void ll_columns(const double* mL, const T* Tp, int ro
 // are issued before the current one is folded.  Per column each wave reduces
 // its 64 lane sums once (DPP), so the reduction is paid once per 64 x R rows.
 template <typename T>
-__global__ __launch_bounds__(256, 4) void last_leg_kernel(const LastLegJob* jobs, int njobs) {
+__global__ __launch_bounds__(256, 4) void last_leg_kernel(const LastLegJob* jobs, int njobs, const double* stop) {
+  if (stopped(stop)) return;
   using S = LLShape<T>;
   constexpr int V = S::V, NV = S::NV;
   // LDS: the 4 waves' column sums [4][nL], then the last leg's message (read
@@ -442,7 +460,8 @@ __global__ __launch_bounds__(256, 4) void last_leg_kernel(const LastLegJob* jobs
 }
 
 // out[e] = sum over blocks of part[blk, e]: 8 groups of 128 columns, fixed order
-__global__ __launch_bounds__(1024) void last_leg_reduce(const LastLegJob* jobs) {
+__global__ __launch_bounds__(1024) void last_leg_reduce(const LastLegJob* jobs, const double* stop) {
+  if (stopped(stop)) return;
   const LastLegJob& job = jobs[blockIdx.x];
   __shared__ double red[8][129];
   const int c = threadIdx.x & 127, g = threadIdx.x >> 7;
@@ -463,7 +482,8 @@ __global__ __launch_bounds__(1024) void last_leg_reduce(const LastLegJob* jobs) 
 }
 
 __global__ __launch_bounds__(256) void meas_norm_kernel(const MeasNormJob* jobs, double alpha,
-                                                        double* delta) {
+                                                        double* delta, const double* stop) {
+  if (stopped(stop)) return;
   const MeasNormJob job = jobs[blockIdx.x];
   const int n = job.n;
   __shared__ double sh[16];
@@ -610,9 +630,9 @@ int launch_dots(const DotJob* jobs, int njobs, hipStream_t s) {
 }
 
 int launch_log_product(const double* x, int n_num, int n_den, const double* delta, int n_delta,
-                       double* res, hipStream_t s) {
+                       double* res, hipStream_t s, double tol, double* ctl) {
   hipLaunchKernelGGL(log_product_kernel, dim3(1), dim3(256), 0, s, x, n_num, n_den, delta,
-                     n_delta, res);
+                     n_delta, res, tol, ctl);
   HPT_LAUNCH_CHECK("log_product_kernel");
   return 0;
 }
@@ -640,16 +660,16 @@ int64_t last_leg_plan(LastLegJob* jobs, int njobs, int is_double, int* max_nl) {
 }
 
 int launch_last_leg(const LastLegJob* jobs_dev, int njobs, int64_t blocks, int max_nl,
-                    int is_double, hipStream_t s) {
+                    int is_double, hipStream_t s, const double* stop) {
   if (njobs <= 0) return 0;
   if (blocks < 1 || blocks > 0x7fffffffll || max_nl < 1 || max_nl > LL_MAXL) return -1;
   const size_t lds = (size_t)5 * max_nl * sizeof(double);
   if (is_double)
-    hipLaunchKernelGGL(last_leg_kernel<double>, dim3((unsigned)blocks), dim3(256), lds, s, jobs_dev, njobs);
+    hipLaunchKernelGGL(last_leg_kernel<double>, dim3((unsigned)blocks), dim3(256), lds, s, jobs_dev, njobs, stop);
   else
-    hipLaunchKernelGGL(last_leg_kernel<float>, dim3((unsigned)blocks), dim3(256), lds, s, jobs_dev, njobs);
+    hipLaunchKernelGGL(last_leg_kernel<float>, dim3((unsigned)blocks), dim3(256), lds, s, jobs_dev, njobs, stop);
   HPT_LAUNCH_CHECK("last_leg_kernel");
-  hipLaunchKernelGGL(last_leg_reduce, dim3(njobs), dim3(1024), 0, s, jobs_dev);
+  hipLaunchKernelGGL(last_leg_reduce, dim3(njobs), dim3(1024), 0, s, jobs_dev, stop);
   HPT_LAUNCH_CHECK("last_leg_reduce");
   return 0;
 }
@@ -683,43 +703,44 @@ int64_t meas_plan(MeasJob* jobs, int njobs, int64_t totals[4]) {
 }
 
 int meas_launch(const MeasJob* jobs_dev, int njobs, const int64_t totals[4], int is_double,
-                double* part, hipStream_t s) {
+                double* part, hipStream_t s, const double* stop) {
   if (njobs <= 0) return 0;
   for (int k = 0; k < 4; ++k)
     if (totals[k] > 0x7fffffffll) return -1;
   if (totals[0] > 0) {
-    hipLaunchKernelGGL(meas_kron_kernel, dim3((unsigned)totals[0]), dim3(256), 0, s, jobs_dev, njobs);
+    hipLaunchKernelGGL(meas_kron_kernel, dim3((unsigned)totals[0]), dim3(256), 0, s, jobs_dev, njobs, stop);
     HPT_LAUNCH_CHECK("meas_kron_kernel");
   }
   if (totals[1] > 0) {
     if (is_double)
       hipLaunchKernelGGL(meas_gemv_n_kernel<double>, dim3((unsigned)totals[1]), dim3(256), 0, s, jobs_dev,
-                         njobs, part);
+                         njobs, part, stop);
     else
       hipLaunchKernelGGL(meas_gemv_n_kernel<float>, dim3((unsigned)totals[1]), dim3(256), 0, s, jobs_dev,
-                         njobs, part);
+                         njobs, part, stop);
     HPT_LAUNCH_CHECK("meas_gemv_n_kernel");
-    hipLaunchKernelGGL(meas_gemv_n_reduce, dim3((unsigned)totals[3]), dim3(256), 0, s, jobs_dev, njobs, part);
+    hipLaunchKernelGGL(meas_gemv_n_reduce, dim3((unsigned)totals[3]), dim3(256), 0, s, jobs_dev, njobs, part,
+                       stop);
     HPT_LAUNCH_CHECK("meas_gemv_n_reduce");
   }
   if (totals[2] > 0) {
     if (is_double)
       hipLaunchKernelGGL(meas_gemv_t_kernel<double>, dim3((unsigned)totals[2]), dim3(256), 0, s, jobs_dev,
-                         njobs, part);
+                         njobs, part, stop);
     else
       hipLaunchKernelGGL(meas_gemv_t_kernel<float>, dim3((unsigned)totals[2]), dim3(256), 0, s, jobs_dev,
-                         njobs, part);
+                         njobs, part, stop);
     HPT_LAUNCH_CHECK("meas_gemv_t_kernel");
   }
-  hipLaunchKernelGGL(meas_gemv_t_reduce, dim3(njobs), dim3(256), 0, s, jobs_dev, part);
+  hipLaunchKernelGGL(meas_gemv_t_reduce, dim3(njobs), dim3(256), 0, s, jobs_dev, part, stop);
   HPT_LAUNCH_CHECK("meas_gemv_t_reduce");
   return 0;
 }
 
 int launch_meas_norm(const MeasNormJob* jobs, int njobs, double alpha, double* delta,
-                     hipStream_t s) {
+                     hipStream_t s, const double* stop) {
   if (njobs <= 0) return 0;
-  hipLaunchKernelGGL(meas_norm_kernel, dim3(njobs), dim3(256), 0, s, jobs, alpha, delta);
+  hipLaunchKernelGGL(meas_norm_kernel, dim3(njobs), dim3(256), 0, s, jobs, alpha, delta, stop);
   HPT_LAUNCH_CHECK("meas_norm_kernel");
   return 0;
 }

@@ -13,6 +13,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "tune.h"
 
 namespace hpt {
 
@@ -124,7 +125,18 @@ __global__ __launch_bounds__(256) void swap_panel_smallb_kernel(const E* __restr
   const int pc = (int)(C - c0 < PC ? C - c0 : PC);
   const E* src = in + (p * C + c0) * B;
   const int n = pc * B;
-  for (int t = threadIdx.x; t < n; t += 256) tile[t / B][t % B] = src[t];
+  // (t / B, t % B) stepped along t without a division per element
+  int j = (int)threadIdx.x / B, b = (int)threadIdx.x % B;
+  const int sj = 256 / B, sb = 256 % B;
+  for (int t = threadIdx.x; t < n; t += 256) {
+    tile[j][b] = src[t];
+    j += sj;
+    b += sb;
+    if (b >= B) {
+      b -= B;
+      ++j;
+    }
+  }
   __syncthreads();
   E* dst = out + p * C * B + c0;
   for (int t = threadIdx.x; t < PC * B; t += 256) {
@@ -150,7 +162,17 @@ __global__ __launch_bounds__(256) void swap_panel_smallc_kernel(const E* __restr
   __syncthreads();
   E* dst = out + (p * B + b0) * C;
   const int n = pb * C;
-  for (int t = threadIdx.x; t < n; t += 256) dst[t] = tile[t % C][t / C];
+  int i = (int)threadIdx.x / C, c = (int)threadIdx.x % C;
+  const int si = 256 / C, sc = 256 % C;
+  for (int t = threadIdx.x; t < n; t += 256) {
+    dst[t] = tile[c][i];
+    i += si;
+    c += sc;
+    if (c >= C) {
+      c -= C;
+      ++i;
+    }
+  }
 }
 
 template <typename E>
@@ -170,6 +192,22 @@ int launch_panel(const void* in, void* out, int64_t B, int64_t C, int64_t P, hip
                        (const E*)in, (E*)out, B, (int)C);
   }
   HPT_LAUNCH_CHECK("swap_panel_kernel");
+  return 0;
+}
+
+// out[a, c, b, p] = in[a, b, c, p] through 64 x 64 LDS tiles of (b, c)
+int launch_tile(const void* in, void* out, int64_t A, int64_t B, int64_t C, int64_t P, int elem, hipStream_t s) {
+  const int64_t tiles_b = ceil_div(B, TT), tiles_c = ceil_div(C, TT);
+  const int64_t slices = A * P;
+  if (slices > 65535 || tiles_b * tiles_c > 0x7fffffff) return -1;
+  dim3 grid((unsigned)(tiles_b * tiles_c), (unsigned)slices);
+  if (elem == 8)
+    hipLaunchKernelGGL(swap_mid_tile_kernel<uint64_t>, grid, dim3(256), 0, s,
+                       (const uint64_t*)in, (uint64_t*)out, A, B, C, tiles_b);
+  else
+    hipLaunchKernelGGL(swap_mid_tile_kernel<uint32_t>, grid, dim3(256), 0, s,
+                       (const uint32_t*)in, (uint32_t*)out, A, B, C, tiles_b);
+  HPT_LAUNCH_CHECK("swap_mid_tile_kernel");
   return 0;
 }
 
@@ -226,24 +264,23 @@ int permute_swap_mid(const void* in, void* out, int64_t A, int64_t B, int64_t C,
     if (elem == 8) return launch_swap_rows<uint64_t>(in, out, A, B, C, P, s);
     return launch_swap_rows<uint32_t>(in, out, A, B, C, P, s);
   }
-  if (elem == 8 && A == 1 && (B <= 128 || C <= 128)) {
-    // float64, the cut leg is the first one (or goes back there): panel
-    // transposes (4.1-4.4 TB/s against 3.3-3.5 for the 64 x 64 tiles; for
-    // float32 the tiles are faster, 3.5 against 2.6 TB/s)
-    return launch_panel<uint64_t>(in, out, B, C, P, s);
+  if (A == 1 && (B <= 128 || C <= 128) && P <= 65535) {
+    // the cut leg is the first one (or goes back there): panel transposes or
+    // 64 x 64 tiles, chosen by the autotuner (default: panels for float64,
+    // 4.1-4.4 TB/s against 3.3-3.5 for the tiles; tiles for float32)
+    TuneCall tc;
+    const int cand = tune_pick(TUNE_PERMUTE_LEAD, elem, B, C * P, 2, &tc);
+    const bool panel = (elem == 8) == (cand == 0);
+    tune_begin(&tc, s);
+    int r;
+    if (panel)
+      r = elem == 8 ? launch_panel<uint64_t>(in, out, B, C, P, s) : launch_panel<uint32_t>(in, out, B, C, P, s);
+    else
+      r = launch_tile(in, out, A, B, C, P, elem, s);
+    tune_end(&tc, s);
+    return r;
   }
-  const int64_t tiles_b = ceil_div(B, TT), tiles_c = ceil_div(C, TT);
-  const int64_t slices = A * P;
-  if (slices > 65535) return -1;
-  dim3 grid((unsigned)(tiles_b * tiles_c), (unsigned)slices);
-  if (elem == 8)
-    hipLaunchKernelGGL(swap_mid_tile_kernel<uint64_t>, grid, dim3(256), 0, s,
-                       (const uint64_t*)in, (uint64_t*)out, A, B, C, tiles_b);
-  else
-    hipLaunchKernelGGL(swap_mid_tile_kernel<uint32_t>, grid, dim3(256), 0, s,
-                       (const uint32_t*)in, (uint32_t*)out, A, B, C, tiles_b);
-  HPT_LAUNCH_CHECK("swap_mid_tile_kernel");
-  return 0;
+  return launch_tile(in, out, A, B, C, P, elem, s);
 }
 
 }  // namespace hpt

@@ -4,7 +4,7 @@
 
 namespace hpt {
 
-// ---- field half-step (row a1): rotate the X, Y Pauli slices of one site
+// ---- field half-step (Sec. "Trotter Decomposition", Eq. trotter): rotate the X, Y Pauli slices of one site
 template <typename T>
 int launch_field(T* psi, int64_t slice, double gxx, double gxy, double gyx, double gyy,
                  hipStream_t s);
@@ -42,11 +42,16 @@ int launch_dots(const DotJob* jobs, int njobs, hipStream_t s);
 // log-space product: res[0] = sum_i sgn_i log|x_i| (sgn = +1 for numerators,
 // -1 for denominators), res[1] = product of signs, res[2] = 1 if any x_i == 0
 // among numerators, res[3] = 1 if any x_i == 0 among denominators,
-// res[4] = max delta over n_delta entries of delta (if delta != null)
+// res[4] = max delta over n_delta entries of delta (if delta != null).
+// Sweep control of the measurement BP (ctl non-null, ctl[0] = stop flag,
+// ctl[1] = sweeps taken): the kernel does nothing once ctl[0] is set, else
+// counts the sweep in ctl[1] and sets ctl[0] when res[4] < tol or res[4] is
+// not finite.  The measurement-sweep launchers below take ctl as `stop` and
+// return at once when it is set, so sweeps queued past convergence are no-ops.
 int launch_log_product(const double* x, int n_num, int n_den, const double* delta, int n_delta,
-                       double* res, hipStream_t s);
+                       double* res, hipStream_t s, double tol = 0.0, double* ctl = nullptr);
 
-// ---- measurement BP (row a9): contraction of a pinned slice with vectors
+// ---- measurement BP (Sec. "Correlation Function via Belief Propagation"): contraction of a pinned slice with vectors
 // on every leg except one.  out[a] = sum_{i,o} T[i + I*(a + nk*o)] x[i] y[o]
 // with x, y Kronecker products of the incoming messages of the legs before
 // and after the output leg.
@@ -69,7 +74,7 @@ struct MeasJob {
 // jobs to the device and calls meas_launch.
 int64_t meas_plan(MeasJob* jobs_host, int njobs, int64_t totals[4]);
 int meas_launch(const MeasJob* jobs_dev, int njobs, const int64_t totals[4], int is_double,
-                double* part, hipStream_t s);
+                double* part, hipStream_t s, const double* stop = nullptr);
 
 // One pass over a pinned slice T (rows x nL, column-major, last leg slowest):
 // P[r] = sum_e T[r, e] mL[e] (T contracted with the last leg's message, for
@@ -92,7 +97,7 @@ int64_t last_leg_blocks(int64_t rows, int is_double);
 // block count, -1 if a job is out of range (nL > 1024, rows >= 2^31 - block)
 int64_t last_leg_plan(LastLegJob* jobs_host, int njobs, int is_double, int* max_nl);
 int launch_last_leg(const LastLegJob* jobs_dev, int njobs, int64_t blocks, int max_nl,
-                    int is_double, hipStream_t s);
+                    int is_double, hipStream_t s, const double* stop = nullptr);
 
 // normalise, sign continuity, damp, normalise; delta[i] = max |mn - mo|
 struct MeasNormJob {
@@ -101,7 +106,7 @@ struct MeasNormJob {
   int n;
 };
 int launch_meas_norm(const MeasNormJob* jobs, int njobs, double alpha, double* delta,
-                     hipStream_t s);
+                     hipStream_t s, const double* stop = nullptr);
 
 // ---- sign weights: z[c + n*p] = sum_r A[r + lda*c] w(r + m*p) for an m x n
 // matrix, p = 0..3, with w the SplitMix64 weights of the gauge-sign rule

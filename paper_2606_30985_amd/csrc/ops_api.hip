@@ -1,12 +1,15 @@
 // Stand-alone C ABI entry points of single steps of the gate update, on
 // caller device buffers (no simulator handle): the float64 Gram of the
-// CholeskyQR first pass (Sec. "Adaptive QR Decomposition", Eq. cholqr).
+// CholeskyQR first pass (Sec. "Adaptive QR Decomposition", Eq. cholqr) and
+// the float32 mode product of the absorb step (Sec. "Gate Update"); the
+// switch and report of the launch-shape autotuner.
 #include <cstdint>
 #include <mutex>
 
 #include "../../include/hpt.h"
 #include "common.h"
 #include "learn.h"
+#include "tune.h"
 
 // Scratch of hpt_gram64_noalloc: the per-split partial tiles live in this
 // file-scope device array (one copy per GPU, held until the process ends)
@@ -96,6 +99,21 @@ int hpt_learn_adam(float* params, float* m, float* v, const float* grad, int32_t
 int hpt_bf16_mfma_sum(const float* a, float c, float* out, void* hip_stream) {
   if (!a || !out) return HPT_EINVAL;
   return bf16_mfma_sum(a, c, out, (hipStream_t)hip_stream) ? HPT_EHIP : HPT_OK;
+}
+
+int hpt_mode_product_f32(const float* src, float* dst, const float* S, int32_t n, int64_t inner, int64_t outer,
+                         void* hip_stream) {
+  if (!src || !dst || !S || n < 1 || n > 128 || inner < 1 || outer < 1) return HPT_EINVAL;
+  if ((inner == 1 && outer < 16) || (inner > 1 && inner < 16) || inner * n >= ((int64_t)1 << 30)) return HPT_EINVAL;
+  const int r = mode_product_f32(S, src, dst, n, inner, outer, (hipStream_t)hip_stream);
+  return r < 0 ? HPT_EHIP : (r == 0 ? HPT_EINVAL : HPT_OK);
+}
+
+int hpt_autotune(int32_t mode) { return tune_set(mode) ? HPT_EINVAL : HPT_OK; }
+
+int hpt_autotune_report(char* buf, uint64_t cap, uint64_t* needed) {
+  if (!buf && cap > 0) return HPT_EINVAL;
+  return tune_report(buf, cap, needed) ? HPT_EINVAL : HPT_OK;
 }
 
 int hpt_gram64_noalloc(const float* X, int64_t m, int32_t n, int64_t ldx, double* G, int64_t ldg,

@@ -59,7 +59,7 @@ class HptConfig(ctypes.Structure):
         ("trap_sweeps", ctypes.c_int32), ("qr_rank_tol", ctypes.c_double),
         ("trap_retry", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("trap_alpha", ctypes.c_double),
         ("model_axes", ctypes.c_int32), ("svd_max_sweeps", ctypes.c_int32),
-        ("meas_init", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1),
+        ("meas_init", ctypes.c_int32), ("meas_graph", ctypes.c_int32),
     ]
 
 
@@ -126,6 +126,9 @@ def _load():
         "hpt_learn_backward": [P, P, P, P, ctypes.c_int64, P, P],
         "hpt_learn_adam": [P, P, P, P, i32, ctypes.c_float, P],
         "hpt_bf16_mfma_sum": [P, ctypes.c_float, P, P],
+        "hpt_mode_product_f32": [P, P, P, i32, ctypes.c_int64, ctypes.c_int64, P],
+        "hpt_autotune": [i32],
+        "hpt_autotune_report": [ctypes.c_char_p, u64, ctypes.POINTER(u64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -149,7 +152,8 @@ EXPORTED = ["hpt_config_default", "hpt_required_bytes", "hpt_state_bytes", "hpt_
             "hpt_checkpoint_bytes", "hpt_checkpoint_save", "hpt_checkpoint_load", "hpt_phase_timing",
             "hpt_phase_read", "hpt_gram64_workspace_bytes", "hpt_gram64", "hpt_gram64_noalloc",
             "hpt_meas_learn_rows", "hpt_meas_features", "hpt_meas_targets", "hpt_set_meas_model",
-            "hpt_learn_forward", "hpt_learn_backward", "hpt_learn_adam", "hpt_bf16_mfma_sum"]
+            "hpt_learn_forward", "hpt_learn_backward", "hpt_learn_adam", "hpt_bf16_mfma_sum",
+            "hpt_mode_product_f32", "hpt_autotune", "hpt_autotune_report"]
 
 HPT_MEM_HOST = 0
 HPT_MEM_DEVICE = 1
@@ -440,6 +444,46 @@ def gram64(X, G, workspace=None, stream=None):
     st = stream if stream is not None else torch.cuda.current_stream(X.device).cuda_stream
     check(lib.hpt_gram64(ctypes.c_void_p(X.data_ptr()), m, n, m, ctypes.c_void_p(G.data_ptr()), G.shape[1],
                          ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.c_void_p(st)), "hpt_gram64")
+
+
+def autotune(mode):
+    """Launch-shape autotuner: 1 on (default), 0 off, 2 forget (hpt_autotune)."""
+    check(lib.hpt_autotune(int(mode)), "hpt_autotune")
+
+
+def autotune_report():
+    """The autotuner's shape classes: a list of (site, (k0, k1, k2), [best ms or
+    None per variant], choice) (hpt_autotune_report)."""
+    need = ctypes.c_uint64()
+    check(lib.hpt_autotune_report(None, 0, ctypes.byref(need)), "hpt_autotune_report")
+    buf = ctypes.create_string_buffer(int(need.value))
+    check(lib.hpt_autotune_report(buf, len(buf), ctypes.byref(need)), "hpt_autotune_report")
+    out = []
+    for line in buf.value.decode().splitlines():
+        head, tail = line.split(":", 1)
+        site, *key = head.split()
+        times, choice = tail.split("->")
+        out.append((site, tuple(int(k) for k in key),
+                    [None if t == "-" else float(t) for t in times.split()], int(choice)))
+    return out
+
+
+def mode_product_f32(src, S, inner, outer, stream=None):
+    """dst[a, j, b] = sum_k S[j, k] src[a, k, b] (hpt_mode_product_f32) for
+    float32 device tensors: src holds inner * n * outer values in column-major
+    order (a fastest), S is n x n column-major (S.T row-major); returns dst of
+    src's shape."""
+    import torch
+    n = S.shape[0]
+    if src.dtype != torch.float32 or S.dtype != torch.float32 or not src.is_contiguous() or not S.is_contiguous():
+        raise ValueError("mode_product_f32: contiguous float32 tensors")
+    if src.numel() != inner * n * outer or S.numel() != n * n:
+        raise ValueError("mode_product_f32: src must hold inner * n * outer values and S n * n")
+    dst = torch.empty_like(src)
+    check(lib.hpt_mode_product_f32(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                   ctypes.c_void_p(S.data_ptr()), n, inner, outer, _stream(src, stream)),
+          "hpt_mode_product_f32")
+    return dst
 
 
 def _stream(t, stream):
