@@ -129,6 +129,17 @@ def pauli_coefficients(O, N):
     return a.real.copy()
 
 
+def pauli_weights(O, N):
+    """n(r) = (sum of a_s^2 over the Pauli strings s with a non-identity letter
+    at site r) / (sum of all a_s^2): the per-site non-identity Pauli weight of
+    Sec. "Operator Spreading and Lightcone Saturation", from the Pauli
+    coefficients of the dense operator."""
+    a = pauli_coefficients(O, N)
+    w = a * a
+    tot = w.sum()
+    return np.array([1.0 - np.take(w, 0, axis=r).sum() / tot for r in range(N)])
+
+
 def zzx_trotter_trajectory(lat: Lattice, J, h, dt, nsteps, centre=None):
     """C(n dt) = Tr[Z_c(n dt) Z_c]/2^N for the ZZ-coupling, X-field model
     H = -J sum ZZ - h sum X with the same symmetric splitting, built literally

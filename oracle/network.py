@@ -343,6 +343,25 @@ class OperatorNetwork:
         self.last_gauge = (sweeps, delta)
         return sweeps, delta
 
+    # -- diagnostic: per-site non-identity Pauli weight ---------------------------------
+    def pauli_weights(self):
+        """BP estimate of n(r, t), the per-site non-identity Pauli weight of
+        Sec. "Operator Spreading and Lightcone Saturation": with the gauge
+        messages of the last gauge BP as the environment of every virtual leg,
+        W_v[p, p'] = sum psi_v[.., p] (x_e M_{e -> v}) psi_v[.., p'] is the
+        weight of the Pauli strings by their letter at v (exact on a tree with
+        converged messages), and n_v = 1 - W_v[I, I] / tr W_v."""
+        out = []
+        for v in range(self.lat.n_sites):
+            psi = self.psi[v]
+            T = psi
+            for pos, (_, u, bu) in enumerate(self.lat.legs[v]):
+                T = mode_product(T, self.M[bu][self.lat.direction(bu, u)], pos)
+            axes = list(range(psi.ndim - 1))
+            W = np.tensordot(psi, T, axes=(axes, axes))
+            out.append(1.0 - W[0, 0] / np.trace(W))
+        return np.array(out)
+
     # -- a9: measurement BP and log-space Bethe -------------------------------------
     def pinned(self):
         out = []
@@ -405,6 +424,25 @@ class OperatorNetwork:
         self.meas_messages = m
         return dict(C=C, log_abs_C=log_abs, sign=sign, meas_sweeps=sweeps, meas_delta=delta,
                     flags=flags, vs=vs, Ze=Ze)
+
+
+def spreading_stats(n, lat, centre):
+    """The spreading measures of Sec. "Spatial operator spreading" from the
+    per-site weights n(r): p(r) = n(r) / sum n, the mean Manhattan radius
+    R_L1 = sum p |r - r_c|_1, the RMS Euclidean radius
+    R_L2 = sqrt(sum p |r - r_c|_2^2) and the spatial entropy fraction
+    S_frac = -sum p ln p / ln(number of sites) (Eq. sfrac; 0 ln 0 = 0)."""
+    n = np.asarray(n, dtype=float)
+    p = n / n.sum()
+    cx, cy = lat.coords(centre)
+    r1 = r2 = ent = 0.0
+    for v in range(lat.n_sites):
+        x, y = lat.coords(v)
+        r1 += p[v] * (abs(x - cx) + abs(y - cy))
+        r2 += p[v] * ((x - cx) ** 2 + (y - cy) ** 2)
+        if p[v] > 0:
+            ent -= p[v] * math.log(p[v])
+    return r1, math.sqrt(r2), ent / math.log(lat.n_sites)
 
 
 def bethe_log_sign(vs, Ze):
