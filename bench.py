@@ -759,6 +759,12 @@ def main():
     hpt.profile_gemm(False)
     phase = sim.phase_read()
     sim.phase_timing(False)
+    # operator spreading of the state the timed region ends on (layer `last`)
+    t0 = time.perf_counter()
+    wts, (rl1, rl2, sfrac) = sim.pauli_weights()
+    spreading = {"layer": last, "R_L1": rl1, "R_L2": rl2, "S_frac": sfrac,
+                 "n_centre": float(wts[((L - 1) // 2) * (L + 1)]), "n_min": float(wts.min()),
+                 "n_max": float(wts.max()), "seconds": time.perf_counter() - t0}
     # 4. single-bond gate updates of each class on the snapshot state (one bond per launch)
     per_class = {}
     classes = bond_classes(L)
@@ -837,6 +843,7 @@ def main():
                    "timed_layers": [r["step"] for r in timed_recs],
                    "meas_graph": args.meas_graph,
                    "autotune": autotune_summary(hpt, args.autotune_report),
+                   "spreading": spreading,
                    "chi_over_bonds_at_snapshot": cst,
                    "centre_bonds_chi": [chis[b] for b in cb],
                    "bond_updates_per_s": n_bonds * phase["layers"] / gate_s if gate_s > 0 else None,

@@ -209,6 +209,21 @@ int hpt_gauge_bp(hpt_sim* sim, int32_t init, int32_t* sweeps, double* delta);
  * test after every sweep. */
 int hpt_measure(hpt_sim* sim, hpt_measurement* out);
 
+/* Per-site non-identity Pauli weight n(r, t) of the current state (Sec.
+ * "Operator Spreading and Lightcone Saturation": the weight of the Pauli
+ * strings with a non-identity letter at r, as a fraction of all), estimated
+ * with the gauge messages of the last gauge BP as the environment of every
+ * virtual leg (exact on a tree): W_r = sum psi_r (x_e M_{e->r}) psi_r over
+ * the virtual legs (4 x 4 on the Pauli leg, float64 Gram),
+ * n[r] = 1 - W_r[I, I] / tr W_r, r = x + Lx y.  stats (may be NULL) receives
+ * the spreading measures of Sec. "Spatial operator spreading" with
+ * p = n / sum n: the mean Manhattan radius sum p |r - r_c|_1, the RMS
+ * Euclidean radius sqrt(sum p |r - r_c|_2^2) and the spatial entropy fraction
+ * -sum p ln p / ln N (Eq. sfrac).  n: host, cap >= N doubles.  Costs about one
+ * gauge-BP sweep; synchronises the stream.  HPT_EINVAL for a null n or
+ * cap < N, HPT_ENUMERIC for a zero or non-finite weight. */
+int hpt_pauli_weights(hpt_sim* sim, double* n, int32_t cap, double* stats);
+
 /* Live bond dimension of one bond. */
 int hpt_get_chi(hpt_sim* sim, int32_t bond, int32_t* chi);
 

@@ -1335,6 +1335,63 @@ int gauge_bp_t(hpt_sim* s, int init, int* sweeps_out, double* delta_out) {
 }
 
 // ---------------------------------------------------------------------------
+// Per-site non-identity Pauli weight n(r, t) (Sec. "Operator Spreading and
+// Lightcone Saturation"): with the gauge messages of the last gauge BP on
+// every virtual leg, W_v = sum psi_v (x_e M_{e->v}) psi_v over the virtual
+// legs is a 4 x 4 float64 Gram on the Pauli leg (mode products, then the leg
+// Gram of the Pauli axis), and n_v = 1 - W_v[I, I] / tr W_v.  The spreading
+// measures of Sec. "Spatial operator spreading" follow on the host:
+// p = n / sum n, R_L1 = sum p |r - r_c|_1, R_L2 = sqrt(sum p |r - r_c|_2^2),
+// S_frac = -sum p ln p / ln(number of sites) (Eq. sfrac).
+template <typename T>
+int pauli_weights_t(hpt_sim* s, double* n_out, double* stats) {
+  if (s->fp32) KR(launch_d2f(s->gmsg, s->gmsg32, 2ll * s->nb * s->chi_max * s->chi_max, s->stream));
+  if (16ll * s->N > s->cv.meas_scr_cap || 16ull * s->N * sizeof(double) + 64 > s->hscratch_bytes) return HPT_ENOMEM;
+  double* W = s->meas_scr;
+  for (int v = 0; v < s->N; ++v) {
+    const SiteInfo& si = s->sites[v];
+    int64_t dims[5];
+    site_dims(s, v, dims);
+    const int nd = si.deg + 1;
+    const T* psi = psi_of<T>(s, v);
+    const T* src = psi;
+    for (int l = 0; l < si.deg; ++l) {
+      T* dst = (T*)s->t[l & 1];
+      const int b = si.bond[l];
+      RC(mode_product<T>(s, src, dst, dims, nd, l, gmsg_T<T>(s, b, dir_from(s, b, si.nbr[l]))));
+      src = dst;
+    }
+    RC(leg_gram<T>(s, psi, src, dims, nd, si.deg, W + 16ll * v));
+  }
+  HPT_HIP(hipMemcpyAsync(s->hscratch, W, 16ull * s->N * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  RC(sync_stream(s));
+  const double* Wh = (const double*)s->hscratch;
+  double tot = 0.0;
+  for (int v = 0; v < s->N; ++v) {
+    const double* w = Wh + 16ll * v;
+    const double tr = w[0] + w[5] + w[10] + w[15];
+    if (!std::isfinite(tr) || !(tr > 0.0)) return HPT_ENUMERIC;
+    n_out[v] = 1.0 - w[0] / tr;
+    tot += n_out[v];
+  }
+  if (stats) {
+    const int Lx = s->cfg.Lx;
+    const int cx = s->centre % Lx, cy = s->centre / Lx;
+    double r1 = 0.0, r2 = 0.0, ent = 0.0;
+    for (int v = 0; v < s->N; ++v) {
+      const double p = tot > 0.0 ? n_out[v] / tot : 0.0;
+      const int dx = v % Lx - cx, dy = v / Lx - cy;
+      r1 += p * (std::abs(dx) + std::abs(dy));
+      r2 += p * (double)(dx * dx + dy * dy);
+      if (p > 0.0) ent -= p * std::log(p);
+    }
+    stats[0] = r1;
+    stats[1] = std::sqrt(r2);
+    stats[2] = ent / std::log((double)s->N);
+  }
+  return 0;
+}
+
 // measurement BP and the log-space Bethe sum (Sec. "Correlation Function via Belief
 // Propagation", Eq. bethe)
 
@@ -2135,6 +2192,11 @@ int hpt_gauge_bp(hpt_sim* s, int32_t init, int32_t* sweeps, double* delta) {
 int hpt_measure(hpt_sim* s, hpt_measurement* out) {
   if (!s || !out) return HPT_EINVAL;
   return s->fp32 ? measure_t<float>(s, out) : measure_t<double>(s, out);
+}
+
+int hpt_pauli_weights(hpt_sim* s, double* n, int32_t cap, double* stats) {
+  if (!s || !n || cap < s->N) return HPT_EINVAL;
+  return s->fp32 ? pauli_weights_t<float>(s, n, stats) : pauli_weights_t<double>(s, n, stats);
 }
 
 int hpt_get_chi(hpt_sim* s, int32_t bond, int32_t* chi) {

@@ -128,6 +128,7 @@ def _load():
         "hpt_bf16_mfma_sum": [P, ctypes.c_float, P, P],
         "hpt_mode_product_f32": [P, P, P, i32, ctypes.c_int64, ctypes.c_int64, P],
         "hpt_autotune": [i32],
+        "hpt_pauli_weights": [P, ctypes.POINTER(dbl), i32, ctypes.POINTER(dbl)],
         "hpt_autotune_report": [ctypes.c_char_p, u64, ctypes.POINTER(u64)],
     }
     for name, args in sig.items():
@@ -153,7 +154,7 @@ EXPORTED = ["hpt_config_default", "hpt_required_bytes", "hpt_state_bytes", "hpt_
             "hpt_phase_read", "hpt_gram64_workspace_bytes", "hpt_gram64", "hpt_gram64_noalloc",
             "hpt_meas_learn_rows", "hpt_meas_features", "hpt_meas_targets", "hpt_set_meas_model",
             "hpt_learn_forward", "hpt_learn_backward", "hpt_learn_adam", "hpt_bf16_mfma_sum",
-            "hpt_mode_product_f32", "hpt_autotune", "hpt_autotune_report"]
+            "hpt_mode_product_f32", "hpt_autotune", "hpt_autotune_report", "hpt_pauli_weights"]
 
 HPT_MEM_HOST = 0
 HPT_MEM_DEVICE = 1
@@ -298,6 +299,16 @@ class Simulator:
         m = HptMeasurement()
         check(lib.hpt_measure(self.h, ctypes.byref(m)), "hpt_measure")
         return m.as_dict()
+
+    def pauli_weights(self):
+        """(n, (R_L1, R_L2, S_frac)): per-site non-identity Pauli weight and the
+        spreading measures (hpt_pauli_weights)."""
+        N = self.cfg.Lx * self.cfg.Ly
+        n = np.zeros(N)
+        st = np.zeros(3)
+        P = ctypes.POINTER(ctypes.c_double)
+        check(lib.hpt_pauli_weights(self.h, n.ctypes.data_as(P), N, st.ctypes.data_as(P)), "hpt_pauli_weights")
+        return n, tuple(st)
 
     def chi(self, b):
         c = ctypes.c_int32()
