@@ -481,6 +481,21 @@ void permuted_dims(const SitePlan& P, int64_t* pd) {
   pd[q] = 4;
 }
 
+// Puts the tensor held in temporary ti into site v's storage.  The largest
+// sites' storage and the temporaries are arena slices of the same size, so
+// there the two slices trade places (the site's old storage becomes the
+// temporary); smaller sites take a device copy of `bytes`.  Site storage is
+// always reached through psi_of, never through a cached address.
+int adopt_temp(hpt_sim* s, int v, int ti, uint64_t bytes) {
+  SiteInfo& si = s->sites[v];
+  if (si.cap == s->cv.tcap) {
+    std::swap(si.psi, s->t[ti]);
+    return 0;
+  }
+  HPT_HIP(hipMemcpyAsync(si.psi, s->t[ti], bytes, hipMemcpyDeviceToDevice, s->stream));
+  return 0;
+}
+
 // Float32 form, direct route (a tall block for CholeskyQR2 and no environment
 // eigenvalue dropped): Xraw = psi with the cut leg moved next to the Pauli leg
 // is kept in the site's storage; its absorbed copy X = Xraw x_e sqrt(M_e)
@@ -516,7 +531,7 @@ int phase_a_direct(hpt_sim* s, int i, BondSlot& sl, SitePlan& P) {
   }
   RC(gram<float>(s, n, m, X, m, sl.qa[i][0]));
   if (i == 0) KR(launch_sign_projection<float>(X, m, m, n, sl.z, s->part, s->cv.part_cap, s->stream));
-  if (need_perm) HPT_HIP(hipMemcpyAsync(psi, xraw, sizeof(float) * m * n, hipMemcpyDeviceToDevice, s->stream));
+  if (need_perm) RC(adopt_temp(s, P.v, 2, sizeof(float) * m * n));
   P.direct = 1;
   P.deferred = 1;
   P.was_deferred = 1;
@@ -865,11 +880,10 @@ int phase_c_site(hpt_sim* s, int b, int i, BondSlot& sl, SitePlan& P, int cn) {
     src = dst;
     ti = 0;
   }
-  if (P.direct) {
+  if (P.direct) {   // src is the reconstruction in t[0]
     int64_t total = 4;
     for (int l = 0; l < P.deg; ++l) total *= dims[l];
-    HPT_HIP(hipMemcpyAsync(psi, src, sizeof(T) * total, hipMemcpyDeviceToDevice, s->stream));
-    return 0;
+    return adopt_temp(s, P.v, 0, sizeof(T) * total);
   }
   // deabsorb with the pseudo-inverse square roots; the last product lands in psi
   for (int e = 0; e < P.nenv; ++e) {
