@@ -26,20 +26,7 @@ LEARN_FEATURES = 16
 LEARN_HIDDEN = 128
 LEARN_PARAMS = LEARN_HIDDEN * LEARN_FEATURES + 2 * LEARN_HIDDEN + 1
 
-FLAGS = {
-    "BP_NOT_CONVERGED_GAUGE": 1 << 0,
-    "BP_NOT_CONVERGED_MEAS": 1 << 1,
-    "TRAP_CANDIDATE": 1 << 2,
-    "NORM_EXPLODED": 1 << 3,
-    "DEGENERATE_CUT": 1 << 4,
-    "PINV_CUT": 1 << 5,
-    "BETHE_ZERO": 1 << 6,
-    "QR_FALLBACK": 1 << 7,
-    "QR_RANK_DEFICIENT": 1 << 8,
-    "TRAP_REMEDIATED": 1 << 9,
-    "TRAP_UNRESOLVED": 1 << 10,
-    "SVD_NOT_CONVERGED": 1 << 11,
-}
+from .flags import FLAGS  # noqa: E402  (the measurement flag bits)
 HPT_AXES_PAPER = 0
 HPT_AXES_ZZX = 1
 
@@ -82,6 +69,12 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libhpt.so is not built ({LIB_PATH}); run __graft_entry__.build() "
                           "or python paper_2606_30985_amd/build.py")
+    # torch first: its HIP runtime is then the one libhpt.so binds to (two
+    # copies of the runtime in one process do not share the device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i32, u64, dbl = ctypes.c_int32, ctypes.c_uint64, ctypes.c_double

@@ -5,7 +5,7 @@ A record is a mapping with the keys the library's hpt_measure fills in:
 C, gate_err, meas_sweeps, meas_delta, flags.  Host post-processing of logged
 records; nothing here runs on the device or touches the simulation."""
 
-from .hpt import FLAGS
+from .flags import FLAGS
 
 TRAP_REMEDIATED = FLAGS["TRAP_REMEDIATED"]
 TRAP_UNRESOLVED = FLAGS["TRAP_UNRESOLVED"]

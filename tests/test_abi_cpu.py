@@ -114,3 +114,22 @@ def test_short_arena_refused_without_touching_the_device(hpt):
     assert hpt.lib.hpt_create(ctypes.byref(c), ctypes.c_void_p(1 << 20), need - 1, None, ctypes.byref(h)) == -2
     assert not h.value
     assert hpt.make_config(model_axes="zzx").model_axes == 1
+
+
+def test_flag_bits_match_the_header():
+    # the flag table the host code uses without loading the library
+    from paper_2606_30985_amd.flags import FLAGS
+    hdr = open(os.path.join(ROOT, "include", "hpt.h")).read()
+    defs = {m.group(1): 1 << int(m.group(2)) for m in re.finditer(r"#define HPT_FLAG_([A-Z_]+)\s+\(1u << (\d+)\)", hdr)}
+    assert defs == FLAGS
+
+
+def test_trap_scan_does_not_load_the_library():
+    # importing the host post-processing must not load libhpt.so (the GPU
+    # runtime it links would be loaded before torch's)
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r); import paper_2606_30985_amd.traps; "
+            "print('paper_2606_30985_amd.hpt' in sys.modules)" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.strip() == "False", r.stdout + r.stderr
