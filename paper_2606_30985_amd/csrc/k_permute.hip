@@ -175,11 +175,98 @@ __global__ __launch_bounds__(256) void swap_panel_smallc_kernel(const E* __restr
   }
 }
 
+// Float32 panels with 16-byte accesses on both sides (the caller checks that
+// every vector is aligned: B and C multiples of 4, 16-byte aligned tensors).
+// 128 x 128 panels (66 KB of LDS): the scattered side moves 512-byte runs.
+// smallb, B <= 128: the panel of all B rows and 128 consecutive c is read as
+// one contiguous block of float4, each b's 128 outputs are written as 32
+// float4.  (j, b) = divmod(4 u, B) once per vector, stepped inside it.
+constexpr int VP = 128;
+__global__ __launch_bounds__(256) void swap_panel_smallb_vec_kernel(const uint32_t* __restrict__ in,
+                                                                    uint32_t* __restrict__ out, int B, int64_t C) {
+  __shared__ uint32_t tile[VP][VP + 1];
+  const int64_t c0 = (int64_t)blockIdx.x * VP, p = blockIdx.y;
+  const int pc = (int)(C - c0 < VP ? C - c0 : VP);   // a multiple of 4 (C is)
+  const uint4* src = (const uint4*)(in + (p * C + c0) * B);
+  const int nu = pc * B / 4;
+  for (int u = threadIdx.x; u < nu; u += 256) {
+    const uint4 v = src[u];
+    int j = 4 * u / B, b = 4 * u - j * B;
+    const uint32_t e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      tile[j][b] = e[q];
+      if (++b == B) {
+        b = 0;
+        ++j;
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t* dst = out + p * C * B + c0;
+  const int nq = pc / 4;
+  for (int w = threadIdx.x; w < nq * B; w += 256) {
+    const int b = w / nq, j = 4 * (w - b * nq);
+    *(uint4*)(dst + (int64_t)b * C + j) = make_uint4(tile[j][b], tile[j + 1][b], tile[j + 2][b], tile[j + 3][b]);
+  }
+}
+
+// smallc, C <= 128: each c's run of 128 consecutive b is read as 32 float4,
+// the panel's outputs (128 b x C, contiguous) are written as float4.
+__global__ __launch_bounds__(256) void swap_panel_smallc_vec_kernel(const uint32_t* __restrict__ in,
+                                                                    uint32_t* __restrict__ out, int64_t B, int C) {
+  __shared__ uint32_t tile[VP][VP + 1];
+  const int64_t b0 = (int64_t)blockIdx.x * VP, p = blockIdx.y;
+  const int pb = (int)(B - b0 < VP ? B - b0 : VP);   // a multiple of 4 (B is)
+  const uint32_t* src = in + p * B * C + b0;
+  const int nq = pb / 4;
+  for (int w = threadIdx.x; w < nq * C; w += 256) {
+    const int c = w / nq, i = 4 * (w - c * nq);
+    const uint4 v = *(const uint4*)(src + (int64_t)c * B + i);
+    tile[c][i] = v.x;
+    tile[c][i + 1] = v.y;
+    tile[c][i + 2] = v.z;
+    tile[c][i + 3] = v.w;
+  }
+  __syncthreads();
+  uint4* dst = (uint4*)(out + (p * B + b0) * C);
+  const int nu = pb * C / 4;
+  for (int u = threadIdx.x; u < nu; u += 256) {
+    int i = 4 * u / C, c = 4 * u - i * C;
+    uint32_t e[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      e[q] = tile[c][i];
+      if (++c == C) {
+        c = 0;
+        ++i;
+      }
+    }
+    dst[u] = make_uint4(e[0], e[1], e[2], e[3]);
+  }
+}
+
 template <typename E>
 int launch_panel(const void* in, void* out, int64_t B, int64_t C, int64_t P, hipStream_t s) {
   // 128 x 64 panels (float32) or 128 x 32 (float64): 33 / 33 KB of LDS
   constexpr int PL = 128, PS = sizeof(E) == 4 ? 64 : 32;
   if (P > 65535) return -1;
+  if (sizeof(E) == 4 && B % 4 == 0 && C % 4 == 0 && ((uintptr_t)in & 15) == 0 && ((uintptr_t)out & 15) == 0 &&
+      (B <= VP || C <= VP)) {
+    if (B <= VP) {
+      const int64_t np = ceil_div(C, VP);
+      if (np > 0x7fffffff) return -1;
+      hipLaunchKernelGGL(swap_panel_smallb_vec_kernel, dim3((unsigned)np, (unsigned)P), dim3(256), 0, s,
+                         (const uint32_t*)in, (uint32_t*)out, (int)B, C);
+    } else {
+      const int64_t np = ceil_div(B, VP);
+      if (np > 0x7fffffff) return -1;
+      hipLaunchKernelGGL(swap_panel_smallc_vec_kernel, dim3((unsigned)np, (unsigned)P), dim3(256), 0, s,
+                         (const uint32_t*)in, (uint32_t*)out, B, (int)C);
+    }
+    HPT_LAUNCH_CHECK("swap_panel_vec_kernel");
+    return 0;
+  }
   if (B <= PL) {
     const int64_t np = ceil_div(C, PS);
     if (np > 0x7fffffff) return -1;
