@@ -44,3 +44,22 @@ def test_config0_fp64_trajectory(hpt):
         print(n, m["C"], recs[n]["C"], d, m["gauge_sweeps"], recs[n]["gauge_sweeps"], flush=True)
         assert d <= 1e-10, (n, m["C"], recs[n]["C"])
     sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sweep_graph_replays_equal_direct_launches(hpt, precision):
+    # the measurement BP replays one captured HIP graph per sweep; against the
+    # same sweeps launched one kernel at a time, every layer's C, sweep count
+    # and residual must agree bit for bit (many replays per measurement, with
+    # the layers' own work and host syncs between them)
+    cfg = dict(Lx=4, Ly=4, chi_max=20, dt=0.1, J=1.0, h=0.9, bp_tol=1e-8, meas_tol=1e-10, precision=precision)
+    a = hpt.Simulator(meas_graph=1, **cfg)
+    b = hpt.Simulator(meas_graph=0, **cfg)
+    for _ in range(12):
+        a.step(1)
+        b.step(1)
+        ma, mb = a.measure(), b.measure()
+        assert ma["C"] == mb["C"] and ma["meas_sweeps"] == mb["meas_sweeps"] and ma["meas_delta"] == mb["meas_delta"]
+        assert ma["meas_sweeps"] > 1
+    a.close()
+    b.close()
