@@ -697,8 +697,20 @@ def main():
         hpt.profile_gemm(True)
     # 1. the run up to the snapshot layer, untimed
     traj = {}
+    # with --profile-all: the algorithmic bytes of every last-leg pass of the
+    # run (each measurement sweep and the Bethe pass read every pinned slice once)
+    ll_acc = {"bytes": 0, "dispatches": 0}
+    elem = 8 if args.precision == "fp64" else 4
+
+    def count_last_leg(rec):
+        if args.profile_all:
+            n = rec["meas_sweeps"] + 1
+            ll_acc["bytes"] += meas_sweep_bytes(chi_stats(sim)[0], L, elem) * n
+            ll_acc["dispatches"] += n
+
     for _ in range(ramp):
         r = run_layer(sim, torch, f"{args.precision} ramp", trace)
+        count_last_leg(r)
         traj[r["step"]] = r
     chis, cst = chi_stats(sim)
     msb = meas_sweep_bytes(chis, L, 8 if args.precision == "fp64" else 4)
@@ -737,6 +749,7 @@ def main():
             torch.full((7,), 3.0, device="cuda").mul_(2.0)
             torch.cuda.synchronize()
         r = run_layer(sim, torch, f"{args.precision} {'timed' if timed else 'warmup'}", trace)
+        count_last_leg(r)
         at = r["step"]
         assert r["step"] == layer, (r["step"], layer)
         # every repetition of a layer from the same snapshot gives the same C, bit for bit
@@ -844,6 +857,7 @@ def main():
                    "meas_graph": args.meas_graph,
                    "autotune": autotune_summary(hpt, args.autotune_report),
                    "spreading": spreading,
+                   "last_leg_algorithmic_bytes_all_layers": ll_acc if args.profile_all else None,
                    "chi_over_bonds_at_snapshot": cst,
                    "centre_bonds_chi": [chis[b] for b in cb],
                    "bond_updates_per_s": n_bonds * phase["layers"] / gate_s if gate_s > 0 else None,
