@@ -28,8 +28,10 @@
  *     handle is left usable after HPT_EINVAL / HPT_ENOMEM / HPT_ESTATE.
  *   - Calls on one handle are stream-ordered on the stream given at create
  *     and are not thread-safe; separate handles are independent.
- *   - No device memory is allocated after hpt_create (Sec. "Zero-Malloc
- *     Simulation Loop").
+ *   - The library allocates no device buffer after hpt_create (Sec.
+ *     "Zero-Malloc Simulation Loop"); the runtime objects it makes later
+ *     (the side stream and graphs of the measurement sweeps, the launch
+ *     autotuner's events) are not buffers of the state.
  */
 #ifndef HPT_H
 #define HPT_H
@@ -58,7 +60,7 @@ extern "C" {
                              round-to-nearest three-way bf16 split of each operand, accumulated
                              in float32 (BF16 split precision); everything else as HPT_FP32_MFMA.
                              On 10x10 chi_max=100 its C(t) departs from the FP64 form by up to
-                             9e-6 over 30 layers (HPT_FP32_MFMA: 4e-6) */
+                             9e-6 over 30 layers (HPT_FP32_MFMA: 8.8e-7) */
 
 /* QR strategy (Sec. "Adaptive QR Decomposition") */
 #define HPT_QR_ADAPTIVE    0  /* CholeskyQR2 for tall blocks, Householder otherwise or on failure */
