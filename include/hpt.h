@@ -60,7 +60,7 @@ extern "C" {
                              round-to-nearest three-way bf16 split of each operand, accumulated
                              in float32 (BF16 split precision); everything else as HPT_FP32_MFMA.
                              On 10x10 chi_max=100 its C(t) departs from the FP64 form by up to
-                             9e-6 over 30 layers (HPT_FP32_MFMA: 8.8e-7) */
+                             1.0e-5 over 30 layers (HPT_FP32_MFMA: 6.2e-7) */
 
 /* QR strategy (Sec. "Adaptive QR Decomposition") */
 #define HPT_QR_ADAPTIVE    0  /* CholeskyQR2 for tall blocks, Householder otherwise or on failure */
