@@ -71,3 +71,18 @@ def test_site_bonds_and_measurement_bytes():
     assert set(cnt.values()) == {2} and len(cnt) == 180
     # all bonds at chi: 64 chi^4 + 32 chi^3 + 4 chi^2 entries
     assert bench.meas_sweep_bytes([100] * 180, 10, 4) == 4 * (64 * 100 ** 4 + 32 * 100 ** 3 + 4 * 100 ** 2)
+
+
+def test_site_bonds_follow_the_lattice_numbering():
+    # the bench's per-site bond lists follow the lattice numbering of the
+    # ABI (checked against the oracle's lattice), and one measurement sweep
+    # reads every site's pinned slice (product of its bond dimensions) once
+    sys.path.insert(0, ROOT)
+    import bench
+    from oracle.lattice import Lattice
+    for L in (2, 3, 10):
+        lat = Lattice(L, L)
+        assert bench.site_bonds(L) == [[b for (_, _, b) in lat.legs[v]] for v in range(L * L)]
+    chis = [100] * 180
+    assert bench.meas_sweep_bytes(chis, 10, 4) == 4 * (64 * 100 ** 4 + 32 * 100 ** 3 + 4 * 100 ** 2)
+    assert bench.meas_sweep_bytes([1] * 180, 10, 8) == 8 * 100
