@@ -1,6 +1,8 @@
-"""Host-only checks of bench.py: the multi-GPU refusal and the counter-based
+"""Host-only checks of bench.py: the multi-GPU refusal, the counter-based
 traffic lookup (reported only while the kernel source matches the hash
-recorded with the counters)."""
+recorded with the counters), the roofline peaks, the lattice bookkeeping
+behind the per-class rates and slice bytes, and the summaries of rocprofv3
+kernel traces and counter runs (on small synthetic CSV files)."""
 
 import os
 import shutil
@@ -86,3 +88,52 @@ def test_site_bonds_follow_the_lattice_numbering():
     chis = [100] * 180
     assert bench.meas_sweep_bytes(chis, 10, 4) == 4 * (64 * 100 ** 4 + 32 * 100 ** 3 + 4 * 100 ** 2)
     assert bench.meas_sweep_bytes([1] * 180, 10, 8) == 8 * 100
+
+
+def _write_csv(path, header, rows):
+    import csv
+    path.parent.mkdir(parents=True, exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_trace_summary_counts_only_the_window_between_the_markers(tmp_path, capsys):
+    sys.path.insert(0, ROOT)
+    import bench
+    hdr = ["Kernel_Name", "Start_Timestamp", "End_Timestamp"]
+    rows = [["hpt::(anonymous namespace)::mode_product_kernel<112, 25>", 0, 50],     # before the first marker
+            ["void marker_kernel()", 100, 110],
+            ["hpt::(anonymous namespace)::mode_product32_kernel<112, 25>", 200, 1200],
+            ["hpt::(anonymous namespace)::mode_product_f64acc_kernel", 1300, 1400],
+            ["hpt::(anonymous namespace)::gram64_kernel<true>", 1500, 3500],
+            ["void marker_kernel()", 4000, 4010],
+            ["hpt::(anonymous namespace)::gram64_kernel<true>", 5000, 9000]]          # after the second marker
+    _write_csv(tmp_path / "run" / "x_kernel_trace.csv", hdr, rows)
+    bench.summarize_trace(str(tmp_path))
+    out = capsys.readouterr().out
+    assert "window: 3 dispatches between the markers" in out
+    assert "kernel busy 0.000 s" in out
+    assert "mode: 1 dispatches, 0.00 ms, average 1.0 us" in out        # the f64acc kernel is its own family
+    assert "mode_f64acc: 1 dispatches" in out
+    assert "gram64: 1 dispatches, 0.00 ms, average 2.0 us" in out
+
+
+def test_pmc_summary_sets_the_calibration_copy_apart(tmp_path, capsys):
+    sys.path.insert(0, ROOT)
+    import bench
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    rows = [[1, "hpt::(anonymous namespace)::permute_generic_kernel(hpt::PermMeta)", "FETCH_SIZE", 1024],
+            [2, "hpt::(anonymous namespace)::mode_product32_kernel<112, 25>(float const*)", "FETCH_SIZE", 10],
+            [3, "hpt::(anonymous namespace)::mode_product_kernel<16, 4>(float const*)", "FETCH_SIZE", 5],
+            [4, "hpt::(anonymous namespace)::mode_product_f64acc_kernel(double const*)", "FETCH_SIZE", 7],
+            [5, "hpt::(anonymous namespace)::permute_generic_kernel(hpt::PermMeta)", "FETCH_SIZE", 3]]
+    _write_csv(tmp_path / "p" / "y_counter_collection.csv", hdr, rows)
+    bench.summarize_pmc(str(tmp_path))
+    out = capsys.readouterr().out.splitlines()
+    assert "FETCH_SIZE calibration_copy 1024" in out
+    assert "FETCH_SIZE mode dispatches 2 sum 1.500000e+01" in out
+    assert "FETCH_SIZE mode_f64acc dispatches 1 sum 7.000000e+00" in out
+    assert "FETCH_SIZE permute dispatches 1 sum 3.000000e+00" in out
+    assert "FETCH_SIZE kernel mode_product32_kernel<112, 25> dispatches 1 sum 1.000000e+01" in out
